@@ -1,0 +1,180 @@
+// Window-statistics ORACLE -- test infrastructure only.
+//
+// This is the plain, slow, obviously correct CPU definition of what the HIP
+// library computes.  Only the tests, the smoke check and the bench's CPU
+// baseline may call it; the product path never does.  It shares no code,
+// header, constant or helper with the HIP library.
+//
+// What it computes (paper, Section IV "Graph Analytics" and Table III, with
+// the caption's rule that the reverse queries swap src and dst):
+//
+//   For one window, the packets are a multiset of (src, dst) pairs.  The
+//   traffic matrix A is the multigraph's count matrix (Section V, last
+//   paragraph, reads the packets as a multi-graph):
+//       A(s, d) = number of packets with source s and destination d.
+//   Row view:    r(s) = sum_d A(s,d)         (packets from source s)
+//                f(s) = #{d : A(s,d) > 0}    (fan-out of source s)
+//   Column view: c(d) = sum_s A(s,d)         (packets to destination d)
+//                g(d) = #{s : A(s,d) > 0}    (fan-in of destination d)
+//
+//   stat[0] valid packets          = sum of A                  (Table III row 1)
+//   stat[1] unique links           = nnz(A)                    (row 2)
+//   stat[2] max link packets       = max of A                  (row 4)
+//   stat[3] unique sources         = #{s : r(s) > 0}           (row 5)
+//   stat[4] max source packets     = max r                     (row 7)
+//   stat[5] max source fan-out     = max f                     (row 9)
+//   stat[6] unique destinations    = #{d : c(d) > 0}           (reverse of row 5)
+//   stat[7] max destination packets= max c                     (reverse of row 7)
+//   stat[8] max destination fan-in = max g                     (reverse of row 9)
+//
+// The maximum over an empty set is 0, so an empty window gives nine zeros.
+// Every pair in the window counts as one valid packet: there is no validity
+// mask at this layer.
+//
+// Implementation: one std::map for A keyed by (src, dst), then one std::map
+// per view built from A's entries.  Windows are independent; the optional
+// thread count only spreads whole windows over threads.
+#include <algorithm>
+#include <atomic>
+#include <cstdint>
+#include <map>
+#include <thread>
+#include <utility>
+#include <vector>
+
+namespace {
+
+struct Totals {
+  uint64_t packets = 0;   // sum of A over the row (or column)
+  uint64_t links = 0;     // number of non-zero entries in the row (or column)
+};
+
+void one_window(const uint32_t* src, const uint32_t* dst, int64_t begin, int64_t end,
+                uint64_t out[9]) {
+  // A(s, d), keyed by the ordered pair (s, d).
+  std::map<std::pair<uint32_t, uint32_t>, uint64_t> A;
+  for (int64_t i = begin; i < end; ++i) A[std::make_pair(src[i], dst[i])] += 1;
+
+  std::map<uint32_t, Totals> rows;     // s -> (r(s), f(s))
+  std::map<uint32_t, Totals> cols;     // d -> (c(d), g(d))
+  uint64_t valid = 0, max_link = 0;
+  for (const auto& e : A) {
+    const uint32_t s = e.first.first;
+    const uint32_t d = e.first.second;
+    const uint64_t a = e.second;       // a > 0 for every stored entry
+    valid += a;
+    max_link = std::max(max_link, a);
+    rows[s].packets += a;
+    rows[s].links += 1;
+    cols[d].packets += a;
+    cols[d].links += 1;
+  }
+
+  uint64_t max_r = 0, max_f = 0, max_c = 0, max_g = 0;
+  for (const auto& e : rows) {
+    max_r = std::max(max_r, e.second.packets);
+    max_f = std::max(max_f, e.second.links);
+  }
+  for (const auto& e : cols) {
+    max_c = std::max(max_c, e.second.packets);
+    max_g = std::max(max_g, e.second.links);
+  }
+
+  out[0] = valid;
+  out[1] = static_cast<uint64_t>(A.size());
+  out[2] = max_link;
+  out[3] = static_cast<uint64_t>(rows.size());
+  out[4] = max_r;
+  out[5] = max_f;
+  out[6] = static_cast<uint64_t>(cols.size());
+  out[7] = max_c;
+  out[8] = max_g;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Nine statistics per window for windows [offsets[w], offsets[w+1]).
+// src, dst, offsets and out are host pointers; out holds 9*num_windows
+// values in the order listed above.  threads <= 1 runs single-threaded.
+// Returns 0, -1 for bad arguments (null pointers, negative count, decreasing
+// or negative offsets); on error out is left untouched.
+int nsgc_oracle_window_stats(const uint32_t* src, const uint32_t* dst,
+                             const int64_t* offsets, int64_t num_windows, uint64_t* out,
+                             int threads) {
+  if (num_windows < 0) return -1;
+  if (num_windows == 0) return 0;
+  if (!offsets || !out) return -1;
+  if (offsets[0] < 0) return -1;
+  for (int64_t w = 0; w < num_windows; ++w)
+    if (offsets[w + 1] < offsets[w]) return -1;
+  if (offsets[num_windows] > offsets[0] && (!src || !dst)) return -1;
+
+  if (threads <= 1 || num_windows == 1) {
+    for (int64_t w = 0; w < num_windows; ++w)
+      one_window(src, dst, offsets[w], offsets[w + 1], out + 9 * w);
+    return 0;
+  }
+  std::atomic<int64_t> next(0);
+  auto worker = [&]() {
+    for (;;) {
+      const int64_t w = next.fetch_add(1);
+      if (w >= num_windows) break;
+      one_window(src, dst, offsets[w], offsets[w + 1], out + 9 * w);
+    }
+  };
+  const int n = static_cast<int>(std::min<int64_t>(threads, num_windows));
+  std::vector<std::thread> pool;
+  pool.reserve(n);
+  for (int t = 0; t < n; ++t) pool.emplace_back(worker);
+  for (auto& t : pool) t.join();
+  return 0;
+}
+
+// The per-entity vectors of one window (Table III rows 3, 6 and 8 and their
+// reverses), as sorted lists.  Used by tests that check intermediate results.
+// Each output array must hold at least (end - begin) entries; the returned
+// counts say how many were written.  Returns 0 or -1.
+int nsgc_oracle_window_entities(const uint32_t* src, const uint32_t* dst, int64_t begin,
+                                int64_t end, uint64_t* link_keys, uint64_t* link_counts,
+                                int64_t* n_links, uint32_t* row_ids, uint64_t* row_packets,
+                                uint64_t* row_links, int64_t* n_rows, uint32_t* col_ids,
+                                uint64_t* col_packets, uint64_t* col_links,
+                                int64_t* n_cols) {
+  if (begin < 0 || end < begin) return -1;
+  if (end > begin && (!src || !dst)) return -1;
+  std::map<std::pair<uint32_t, uint32_t>, uint64_t> A;
+  for (int64_t i = begin; i < end; ++i) A[std::make_pair(src[i], dst[i])] += 1;
+  std::map<uint32_t, Totals> rows, cols;
+  int64_t k = 0;
+  for (const auto& e : A) {
+    link_keys[k] = (static_cast<uint64_t>(e.first.first) << 32) | e.first.second;
+    link_counts[k] = e.second;
+    ++k;
+    rows[e.first.first].packets += e.second;
+    rows[e.first.first].links += 1;
+    cols[e.first.second].packets += e.second;
+    cols[e.first.second].links += 1;
+  }
+  *n_links = k;
+  k = 0;
+  for (const auto& e : rows) {
+    row_ids[k] = e.first;
+    row_packets[k] = e.second.packets;
+    row_links[k] = e.second.links;
+    ++k;
+  }
+  *n_rows = k;
+  k = 0;
+  for (const auto& e : cols) {
+    col_ids[k] = e.first;
+    col_packets[k] = e.second.packets;
+    col_links[k] = e.second.links;
+    ++k;
+  }
+  *n_cols = k;
+  return 0;
+}
+
+}  // extern "C"
