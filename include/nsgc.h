@@ -1,0 +1,177 @@
+/*
+ * nsgc.h -- per-window traffic-matrix statistics on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (arXiv 2509.03653, Section IV "Graph Analytics", Table III;
+ * the reverse queries swap src and dst, Table III caption).  A window is a
+ * multiset of (src, dst) packets with 32-bit anonymized addresses; its traffic
+ * matrix A counts packets per pair, A(s,d) = #{packets with src s, dst d}
+ * (the packets form a multigraph, Section V).  With row sums r(s), row
+ * non-zero counts f(s), column sums c(d) and column non-zero counts g(d):
+ *
+ *   valid_packets           = sum of A                 (Table III, row 1)
+ *   unique_links            = nnz(A)                   (row 2)
+ *   max_link_packets        = max of A                 (row 4)
+ *   unique_sources          = #{s : r(s) > 0}          (row 5)
+ *   max_source_packets      = max r                    (row 7)
+ *   max_source_fanout       = max f                    (row 9)
+ *   unique_destinations     = #{d : c(d) > 0}          (row 5, reversed)
+ *   max_destination_packets = max c                    (row 7, reversed)
+ *   max_destination_fanin   = max g                    (row 9, reversed)
+ *
+ * Maxima over an empty set are 0: an empty window yields nine zeros.  Every
+ * pair in a window is a valid packet (there is no validity mask at this layer).
+ * All results are exact integers; they do not depend on batching, tiering,
+ * tuning or the order of packets.
+ *
+ * Conventions for every entry point:
+ *   - src, dst: DEVICE pointers to uint32 arrays, caller-owned, read-only;
+ *     packet i is (src[i], dst[i]).
+ *   - window_offsets: HOST pointer to num_windows+1 int64 values, caller-owned,
+ *     read during the call only.  Window w is packets
+ *     [window_offsets[w], window_offsets[w+1]).  Offsets must be >= 0 and
+ *     non-decreasing; offsets[0] may be non-zero; empty windows are legal.
+ *     A window may hold at most 2^32 - 1 packets.
+ *   - out_stats: DEVICE pointer to num_windows nsgc_stats (8-byte aligned),
+ *     caller-owned, fully overwritten.
+ *   - stream: the HIP stream the work is enqueued on (0 = null stream).  The
+ *     call returns after enqueueing; results are valid once the stream has
+ *     reached that point.  Input buffers must stay alive and unmodified until
+ *     then.
+ *   - Argument errors are reported synchronously with nothing enqueued and
+ *     out_stats untouched.  A HIP runtime failure returns NSGC_ERR_HIP and
+ *     nsgc_last_hip_error() gives the hipError_t.
+ *   - The library keeps per-(device, stream) workspaces, so calls on
+ *     different streams may overlap; calls on one stream run in order.  All
+ *     entry points are thread-safe.
+ */
+#ifndef NSGC_H_
+#define NSGC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One window's statistics, 72 bytes, in Table III order (see above). */
+typedef struct nsgc_stats {
+  uint64_t valid_packets;
+  uint64_t unique_links;
+  uint64_t max_link_packets;
+  uint64_t unique_sources;
+  uint64_t max_source_packets;
+  uint64_t max_source_fanout;
+  uint64_t unique_destinations;
+  uint64_t max_destination_packets;
+  uint64_t max_destination_fanin;
+} nsgc_stats;
+
+typedef enum nsgc_status {
+  NSGC_OK = 0,
+  NSGC_ERR_INVALID_ARG = -1,  /* null pointer, negative count, misaligned out */
+  NSGC_ERR_BAD_OFFSETS = -2,  /* negative/decreasing offsets, window >= 2^32 */
+  NSGC_ERR_NO_MEMORY = -3,    /* workspace allocation failed or exceeds limit */
+  NSGC_ERR_HIP = -4,          /* HIP runtime error, see nsgc_last_hip_error() */
+  NSGC_ERR_INTERNAL = -5,
+  NSGC_ERR_CAPTURING = -6     /* would allocate while the stream is capturing */
+} nsgc_status;
+
+/*
+ * Batched form.  All windows of the call are planned together and processed
+ * by one sequence of persistent kernel launches: tiny windows entirely in LDS,
+ * the others by hash partitioning of the packets into LDS-sized link buckets,
+ * link aggregation per bucket, then row and column aggregation of the
+ * de-duplicated links (Table III rows 1-9 and their reverses, per window).
+ */
+int nsgc_window_stats(const uint32_t* src, const uint32_t* dst,
+                      const int64_t* window_offsets, int64_t num_windows,
+                      nsgc_stats* out_stats, void* stream);
+
+/*
+ * Plain form: the same statistics, one window per launch sequence (each
+ * window is planned and launched on its own, in order).  Same arguments and
+ * results as nsgc_window_stats; kept as the per-window baseline.
+ */
+int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
+                            const int64_t* window_offsets, int64_t num_windows,
+                            nsgc_stats* out_stats, void* stream);
+
+/* Human-readable text for a status code (static storage, never NULL). */
+const char* nsgc_status_string(int status);
+
+/* The hipError_t behind the last NSGC_ERR_HIP returned on this thread. */
+int nsgc_last_hip_error(void);
+
+/*
+ * Pre-size the workspace of (current device, stream) for batches of up to
+ * max_packets packets in up to max_windows windows, so that later calls
+ * within those limits allocate nothing.  Returns NSGC_OK or NSGC_ERR_*.
+ */
+int nsgc_reserve(int64_t max_packets, int64_t max_windows, void* stream);
+
+/* Release all workspaces of the current device (waits for the device). */
+int nsgc_release(void);
+
+/*
+ * Tuning.  The planner's knobs, per window-size class (class k holds windows
+ * with 2^k <= packets < 2^(k+1); class 0 also holds empty windows).
+ * Every setting gives identical statistics; only speed changes.
+ */
+typedef struct nsgc_tune_class {
+  int32_t link_target;      /* packets per link bucket (sets the bucket count) */
+  int32_t row_target;       /* packets per row bucket */
+  int32_t col_target;       /* packets per column bucket */
+  int32_t reserved;
+} nsgc_tune_class;
+
+typedef struct nsgc_tune {
+  int32_t small_max;        /* windows with <= small_max packets run entirely in
+                               LDS, one workgroup each (0..2048) */
+  int32_t tile_log2;        /* partition tile: 2^tile_log2 packets (11..14) */
+  int32_t link_slots_log2;  /* LDS link table: 2^k slots (10..13) */
+  int32_t rc_slots_log2;    /* LDS row/column table: 2^k slots (10..13) */
+  int32_t blocks_per_cu;    /* persistent grid: workgroups per compute unit (1..16) */
+  int32_t max_buckets_log2; /* cap on link/row/column buckets per window (0..12) */
+  int32_t reserved[2];
+  nsgc_tune_class cls[33];
+} nsgc_tune;
+
+/* Current tuning of the calling process (defaults until set). */
+int nsgc_get_tune(nsgc_tune* out);
+/* Validate and install a tuning; NSGC_ERR_INVALID_ARG leaves it unchanged. */
+int nsgc_set_tune(const nsgc_tune* tune);
+/* Built-in defaults. */
+int nsgc_default_tune(nsgc_tune* out);
+
+/*
+ * Host-only planner inspection (no device work, usable without a GPU).
+ * Plans num_windows windows under the current tuning and writes, per window,
+ * the tier (0 = empty, 1 = small/LDS, 2 = partitioned), the log2 bucket
+ * counts (link, row, column) and the number of partition tiles, plus the
+ * workspace bytes the batch needs.  Any output pointer may be NULL.
+ */
+int nsgc_plan_inspect(const int64_t* window_offsets, int64_t num_windows,
+                      int32_t* tier, int32_t* log2_link_buckets,
+                      int32_t* log2_row_buckets, int32_t* log2_col_buckets,
+                      int64_t* tiles, int64_t* workspace_bytes);
+
+/*
+ * Graph form: a reusable hipGraph of the batched form with its own workspace
+ * sized for up to max_packets packets and max_windows windows.  Launching
+ * replays the captured graph (plan upload + persistent kernels, fixed grids);
+ * only the plan's contents change between launches, so any batch within the
+ * limits reuses it.  Launches of one graph object must not overlap in time on
+ * different streams; one stream per graph object is the intended use.
+ */
+typedef struct nsgc_graph nsgc_graph;
+int nsgc_graph_create(int64_t max_packets, int64_t max_windows, nsgc_graph** out);
+int nsgc_graph_launch(nsgc_graph* g, const uint32_t* src, const uint32_t* dst,
+                      const int64_t* window_offsets, int64_t num_windows,
+                      nsgc_stats* out_stats, void* stream);
+int nsgc_graph_destroy(nsgc_graph* g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSGC_H_ */

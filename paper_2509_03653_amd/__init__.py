@@ -1,0 +1,300 @@
+"""Per-window traffic-matrix statistics on AMD Instinct MI355X (gfx950).
+
+Thin binding over the C ABI of ``libnsgc.so`` (``include/nsgc.h``): argument
+marshalling only.  Every step of the computation runs in the library's HIP
+kernels; PyTorch supplies device memory and streams.  There is no CPU
+fallback: calls fail if the library is not built or the tensors are not on a
+GPU.
+
+Statistics per window, in order (arXiv 2509.03653, Table III and its src/dst
+reverse): valid packets, unique links, max link packets, unique sources, max
+source packets, max source fan-out, unique destinations, max destination
+packets, max destination fan-in.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnsgc.so")
+
+STAT_NAMES = (
+    "valid_packets",
+    "unique_links",
+    "max_link_packets",
+    "unique_sources",
+    "max_source_packets",
+    "max_source_fanout",
+    "unique_destinations",
+    "max_destination_packets",
+    "max_destination_fanin",
+)
+
+NSGC_OK = 0
+STATUS = {
+    0: "NSGC_OK",
+    -1: "NSGC_ERR_INVALID_ARG",
+    -2: "NSGC_ERR_BAD_OFFSETS",
+    -3: "NSGC_ERR_NO_MEMORY",
+    -4: "NSGC_ERR_HIP",
+    -5: "NSGC_ERR_INTERNAL",
+    -6: "NSGC_ERR_CAPTURING",
+}
+
+# Every function declared in include/nsgc.h.
+EXPORTS = (
+    "nsgc_window_stats",
+    "nsgc_window_stats_plain",
+    "nsgc_status_string",
+    "nsgc_last_hip_error",
+    "nsgc_reserve",
+    "nsgc_release",
+    "nsgc_get_tune",
+    "nsgc_set_tune",
+    "nsgc_default_tune",
+    "nsgc_plan_inspect",
+    "nsgc_graph_create",
+    "nsgc_graph_launch",
+    "nsgc_graph_destroy",
+)
+
+
+class NsgcError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        text = STATUS.get(status, str(status))
+        detail = ""
+        try:
+            detail = _lib().nsgc_status_string(status).decode()
+            if status == -4:
+                detail += f" (hipError {_lib().nsgc_last_hip_error()})"
+        except Exception:  # pragma: no cover
+            pass
+        super().__init__(f"{what}: {text}: {detail}")
+
+
+class TuneClass(ctypes.Structure):
+    _fields_ = [("link_target", ctypes.c_int32), ("row_target", ctypes.c_int32),
+                ("col_target", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [
+        ("small_max", ctypes.c_int32),
+        ("tile_log2", ctypes.c_int32),
+        ("link_slots_log2", ctypes.c_int32),
+        ("rc_slots_log2", ctypes.c_int32),
+        ("blocks_per_cu", ctypes.c_int32),
+        ("max_buckets_log2", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
+        ("cls", TuneClass * 33),
+    ]
+
+    SCALARS = ("small_max", "tile_log2", "link_slots_log2", "rc_slots_log2",
+               "blocks_per_cu", "max_buckets_log2")
+
+    def to_dict(self) -> dict:
+        d = {k: int(getattr(self, k)) for k in self.SCALARS}
+        d["cls"] = [[int(c.link_target), int(c.row_target), int(c.col_target)] for c in self.cls]
+        return d
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Tune":
+        t = cls()
+        _check(_lib().nsgc_default_tune(ctypes.byref(t)), "nsgc_default_tune")
+        for k in cls.SCALARS:
+            if k in d:
+                setattr(t, k, int(d[k]))
+        for i, row in enumerate(d.get("cls", [])):
+            t.cls[i].link_target, t.cls[i].row_target, t.cls[i].col_target = (int(x) for x in row)
+        return t
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                "python paper_2509_03653_amd/_build.py (there is no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        lib.nsgc_window_stats.argtypes = [vp, vp, vp, i64, vp, vp]
+        lib.nsgc_window_stats.restype = i32
+        lib.nsgc_window_stats_plain.argtypes = [vp, vp, vp, i64, vp, vp]
+        lib.nsgc_window_stats_plain.restype = i32
+        lib.nsgc_status_string.argtypes = [i32]
+        lib.nsgc_status_string.restype = ctypes.c_char_p
+        lib.nsgc_last_hip_error.argtypes = []
+        lib.nsgc_last_hip_error.restype = i32
+        lib.nsgc_reserve.argtypes = [i64, i64, vp]
+        lib.nsgc_reserve.restype = i32
+        lib.nsgc_release.argtypes = []
+        lib.nsgc_release.restype = i32
+        lib.nsgc_get_tune.argtypes = [ctypes.POINTER(Tune)]
+        lib.nsgc_get_tune.restype = i32
+        lib.nsgc_set_tune.argtypes = [ctypes.POINTER(Tune)]
+        lib.nsgc_set_tune.restype = i32
+        lib.nsgc_default_tune.argtypes = [ctypes.POINTER(Tune)]
+        lib.nsgc_default_tune.restype = i32
+        lib.nsgc_plan_inspect.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+        lib.nsgc_plan_inspect.restype = i32
+        lib.nsgc_graph_create.argtypes = [i64, i64, ctypes.POINTER(vp)]
+        lib.nsgc_graph_create.restype = i32
+        lib.nsgc_graph_launch.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+        lib.nsgc_graph_launch.restype = i32
+        lib.nsgc_graph_destroy.argtypes = [vp]
+        lib.nsgc_graph_destroy.restype = i32
+        _LIB = lib
+    return _LIB
+
+
+def library():
+    """The loaded ``libnsgc.so`` (ctypes handle)."""
+    return _lib()
+
+
+def _check(rc: int, what: str):
+    if rc != NSGC_OK:
+        raise NsgcError(rc, what)
+
+
+def _offsets(offsets) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+
+
+def _device_u32(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on a GPU")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on a GPU (there is no CPU path)")
+    if t.dtype not in (torch.int32, torch.uint32):
+        raise TypeError(f"{name} must be int32 or uint32 (32-bit addresses)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _stream_handle(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _run(fn, what, src, dst, offsets, out, stream):
+    import torch
+    src = _device_u32(src, "src")
+    dst = _device_u32(dst, "dst")
+    if src.device != dst.device:
+        raise ValueError("src and dst must be on the same device")
+    off = _offsets(offsets)
+    w = len(off) - 1
+    if w < 0:
+        raise ValueError("offsets needs at least one entry")
+    if w > 0 and (off[-1] > src.numel() or off[-1] > dst.numel()):
+        raise ValueError("offsets run past the packet arrays")
+    if out is None:
+        out = torch.empty((w, 9), dtype=torch.int64, device=src.device)
+    elif out.shape != (w, 9) or out.dtype != torch.int64 or not out.is_contiguous() or out.device != src.device:
+        raise ValueError("out must be a contiguous (W, 9) int64 tensor on the packets' device")
+    with torch.cuda.device(src.device):
+        rc = fn(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                ctypes.c_void_p(off.ctypes.data), w, ctypes.c_void_p(out.data_ptr()),
+                _stream_handle(stream, src.device))
+    _check(rc, what)
+    return out
+
+
+def window_stats(src, dst, offsets, out=None, stream=None):
+    """Batched form (``nsgc_window_stats``): one (W, 9) int64 tensor, enqueued
+    on ``stream`` (default: the current stream)."""
+    return _run(_lib().nsgc_window_stats, "nsgc_window_stats", src, dst, offsets, out, stream)
+
+
+def window_stats_plain(src, dst, offsets, out=None, stream=None):
+    """Plain form (``nsgc_window_stats_plain``): one launch sequence per window."""
+    return _run(_lib().nsgc_window_stats_plain, "nsgc_window_stats_plain", src, dst, offsets,
+                out, stream)
+
+
+def reserve(max_packets: int, max_windows: int, stream=None):
+    import torch
+    _check(_lib().nsgc_reserve(int(max_packets), int(max_windows),
+                               _stream_handle(stream, torch.cuda.current_device())),
+           "nsgc_reserve")
+
+
+def release():
+    _check(_lib().nsgc_release(), "nsgc_release")
+
+
+def get_tune() -> Tune:
+    t = Tune()
+    _check(_lib().nsgc_get_tune(ctypes.byref(t)), "nsgc_get_tune")
+    return t
+
+
+def default_tune() -> Tune:
+    t = Tune()
+    _check(_lib().nsgc_default_tune(ctypes.byref(t)), "nsgc_default_tune")
+    return t
+
+
+def set_tune(t: Tune):
+    _check(_lib().nsgc_set_tune(ctypes.byref(t)), "nsgc_set_tune")
+
+
+def plan_inspect(offsets) -> dict:
+    """Host-only view of the planner's decisions for a batch (no GPU needed)."""
+    off = _offsets(offsets)
+    w = len(off) - 1
+    n = max(w, 1)
+    tier = np.zeros(n, np.int32)
+    lb = np.zeros(n, np.int32)
+    lr = np.zeros(n, np.int32)
+    lc = np.zeros(n, np.int32)
+    tiles = np.zeros(n, np.int64)
+    wsb = np.zeros(1, np.int64)
+    rc = _lib().nsgc_plan_inspect(
+        ctypes.c_void_p(off.ctypes.data), w, ctypes.c_void_p(tier.ctypes.data),
+        ctypes.c_void_p(lb.ctypes.data), ctypes.c_void_p(lr.ctypes.data),
+        ctypes.c_void_p(lc.ctypes.data), ctypes.c_void_p(tiles.ctypes.data),
+        ctypes.c_void_p(wsb.ctypes.data))
+    _check(rc, "nsgc_plan_inspect")
+    return {"tier": tier[:w], "log2_link_buckets": lb[:w], "log2_row_buckets": lr[:w],
+            "log2_col_buckets": lc[:w], "tiles": tiles[:w], "workspace_bytes": int(wsb[0])}
+
+
+class Graph:
+    """Reusable captured graph of the batched form (``nsgc_graph_*``)."""
+
+    def __init__(self, max_packets: int, max_windows: int):
+        h = ctypes.c_void_p()
+        _check(_lib().nsgc_graph_create(int(max_packets), int(max_windows), ctypes.byref(h)),
+               "nsgc_graph_create")
+        self._h = h
+
+    def launch(self, src, dst, offsets, out=None, stream=None):
+        if self._h is None:
+            raise RuntimeError("graph destroyed")
+        fn = lambda *a: _lib().nsgc_graph_launch(self._h, *a)  # noqa: E731
+        return _run(fn, "nsgc_graph_launch", src, dst, offsets, out, stream)
+
+    def close(self):
+        if self._h is not None:
+            _check(_lib().nsgc_graph_destroy(self._h), "nsgc_graph_destroy")
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,617 @@
+// C ABI of the window-statistics library (declared in include/nsgc.h).
+//
+// Host side of every call: validate the arguments, plan the batch (tiers,
+// bucket counts, items, workspace layout), upload the plan through a pinned
+// staging buffer with one async copy, and launch the persistent kernels on the
+// caller's stream.  Workspaces and plan buffers are cached per (device,
+// stream) so calls on different streams can overlap.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "nsgc.h"
+#include "nsgc_planner.hpp"
+
+namespace nsgc {
+hipError_t launch_small(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
+hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t grid, size_t lds,
+                            hipStream_t s);
+hipError_t launch_links(const nsgc_dev_plan* P, uint32_t max_buckets, uint32_t grid, size_t lds,
+                        hipStream_t s);
+hipError_t launch_rowcol(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
+size_t lds_small_bytes(uint32_t slots_log2);
+size_t lds_part_bytes(uint32_t max_buckets);
+size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_buckets);
+size_t lds_rc_bytes(uint32_t slots_log2);
+hipError_t allow_large_lds(size_t bytes);
+}  // namespace nsgc
+
+using namespace nsgc;
+
+namespace {
+
+thread_local int t_last_hip_error = 0;
+
+int hip_fail(hipError_t e) {
+  t_last_hip_error = int(e);
+  return NSGC_ERR_HIP;
+}
+
+#define NSGC_HIP(expr)                       \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+constexpr int kStages = 4;
+
+// Device buffers and staging of one (device, stream) pair or graph instance.
+struct Slot {
+  char* plan_dev = nullptr;
+  size_t plan_cap = 0;
+  char* ws = nullptr;
+  size_t ws_cap = 0;
+  char* stage[kStages] = {};
+  size_t stage_cap[kStages] = {};
+  hipEvent_t ev[kStages] = {};
+  bool ev_used[kStages] = {};
+  int next = 0;
+};
+
+struct DevCtx {
+  int device = 0;
+  int cus = 256;
+  size_t lds_limit = 65536;
+  std::map<hipStream_t, Slot*> slots;
+};
+
+std::mutex g_mu;
+std::map<int, DevCtx*> g_devs;
+nsgc_tune g_tune;
+bool g_tune_set = false;
+
+const nsgc_tune& current_tune() {
+  if (!g_tune_set) {
+    default_tune(&g_tune);
+    g_tune_set = true;
+  }
+  return g_tune;
+}
+
+int get_ctx(DevCtx** out) {
+  int dev = 0;
+  NSGC_HIP(hipGetDevice(&dev));
+  auto it = g_devs.find(dev);
+  if (it != g_devs.end()) {
+    *out = it->second;
+    return NSGC_OK;
+  }
+  DevCtx* c = new DevCtx;
+  c->device = dev;
+  hipDeviceProp_t prop;
+  NSGC_HIP(hipGetDeviceProperties(&prop, dev));
+  c->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->lds_limit = prop.sharedMemPerBlock > 0 ? size_t(prop.sharedMemPerBlock) : 65536;
+  // gfx950 gives a workgroup up to the whole 160 KB LDS of its compute unit
+  int per_cu = 0;
+  if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+          hipSuccess &&
+      per_cu > 0)
+    c->lds_limit = std::max(c->lds_limit, size_t(per_cu));
+  NSGC_HIP(allow_large_lds(c->lds_limit));
+  g_devs[dev] = c;
+  *out = c;
+  return NSGC_OK;
+}
+
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+
+// Grow a device buffer; waits for `s` first since queued work may still use it.
+int ensure_device(char** buf, size_t* cap, size_t need, hipStream_t s) {
+  if (*cap >= need && *buf) return NSGC_OK;
+  if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
+  size_t want = std::max(need, *cap + *cap / 4);
+  if (*buf) {
+    NSGC_HIP(hipStreamSynchronize(s));
+    NSGC_HIP(hipFree(*buf));
+    *buf = nullptr;
+    *cap = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    e = hipMalloc(&p, need);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return NSGC_ERR_NO_MEMORY;
+    }
+    want = need;
+  }
+  *buf = static_cast<char*>(p);
+  *cap = want;
+  return NSGC_OK;
+}
+
+// A staging buffer that no queued copy still reads.
+int take_stage(Slot* sl, size_t need, hipStream_t s, int* idx) {
+  const int k = sl->next;
+  if (sl->ev_used[k]) NSGC_HIP(hipEventSynchronize(sl->ev[k]));
+  if (!sl->ev[k]) NSGC_HIP(hipEventCreateWithFlags(&sl->ev[k], hipEventDisableTiming));
+  if (sl->stage_cap[k] < need) {
+    if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
+    if (sl->stage[k]) NSGC_HIP(hipHostFree(sl->stage[k]));
+    sl->stage[k] = nullptr;
+    sl->stage_cap[k] = 0;
+    const size_t want = std::max<size_t>(need * 2, 4096);
+    void* p = nullptr;
+    NSGC_HIP(hipHostMalloc(&p, want, hipHostMallocDefault));
+    sl->stage[k] = static_cast<char*>(p);
+    sl->stage_cap[k] = want;
+  }
+  *idx = k;
+  sl->next = (k + 1) % kStages;
+  return NSGC_OK;
+}
+
+struct Launch {
+  uint32_t grid_cap;
+  size_t lds_small, lds_part, lds_link, lds_rc;
+  uint32_t max_buckets;
+};
+
+Launch launch_params(const DevCtx* c, const nsgc_tune& t) {
+  Launch L;
+  L.grid_cap = uint32_t(c->cus) * uint32_t(t.blocks_per_cu);
+  L.max_buckets = 1u << t.max_buckets_log2;
+  const uint32_t small_log2 =
+      uint32_t(std::max(ceil_log2(uint64_t(std::max(t.small_max, 1)) * 2), 6));
+  L.lds_small = lds_small_bytes(small_log2);
+  L.lds_part = lds_part_bytes(L.max_buckets);
+  L.lds_link = lds_link_bytes(uint32_t(t.link_slots_log2), L.max_buckets);
+  L.lds_rc = lds_rc_bytes(uint32_t(t.rc_slots_log2));
+  return L;
+}
+
+int check_lds(const DevCtx* c, const Launch& L) {
+  const size_t m = std::max(std::max(L.lds_small, L.lds_part), std::max(L.lds_link, L.lds_rc));
+  return m <= c->lds_limit ? NSGC_OK : NSGC_ERR_INVALID_ARG;
+}
+
+// Enqueue the kernels of one uploaded plan.  `fixed_grid` launches every
+// kernel with the full persistent grid (graph capture); otherwise grids are
+// trimmed to the item counts and empty phases are skipped.
+int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch& L,
+                    uint32_t tile_log2, hipStream_t s, bool fixed_grid) {
+  auto grid = [&](uint32_t items) { return fixed_grid ? L.grid_cap : std::min(items, L.grid_cap); };
+  if (fixed_grid || !hp.small.empty())
+    NSGC_HIP(launch_small(dplan, grid(uint32_t(hp.small.size())), L.lds_small, s));
+  if (fixed_grid || !hp.win.empty()) {
+    NSGC_HIP(launch_partition(dplan, tile_log2, grid(hp.itemsA), L.lds_part, s));
+    NSGC_HIP(launch_links(dplan, L.max_buckets, grid(hp.itemsB), L.lds_link, s));
+    NSGC_HIP(launch_rowcol(dplan, grid(hp.itemsC), L.lds_rc, s));
+  }
+  return NSGC_OK;
+}
+
+int validate_common(const uint32_t* src, const uint32_t* dst, const int64_t* offsets,
+                    int64_t num_windows, const void* out) {
+  if (num_windows < 0) return NSGC_ERR_INVALID_ARG;
+  if (num_windows == 0) return NSGC_OK;
+  if (!offsets || !out) return NSGC_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(out) % 8 != 0) return NSGC_ERR_INVALID_ARG;
+  const int rc = validate_offsets(offsets, num_windows);
+  if (rc != NSGC_OK) return rc;
+  if (offsets[num_windows] > offsets[0] && (!src || !dst)) return NSGC_ERR_INVALID_ARG;
+  return NSGC_OK;
+}
+
+int get_slot(DevCtx* c, hipStream_t s, Slot** out) {
+  auto it = c->slots.find(s);
+  if (it != c->slots.end()) {
+    *out = it->second;
+    return NSGC_OK;
+  }
+  Slot* sl = new Slot;
+  c->slots[s] = sl;
+  *out = sl;
+  return NSGC_OK;
+}
+
+// Upload one plan into slot `sl` and launch it.
+int run_plan(DevCtx* c, Slot* sl, const HostPlan& hp, const nsgc_tune& t, const uint32_t* src,
+             const uint32_t* dst, void* out, hipStream_t s) {
+  const Launch L = launch_params(c, t);
+  int rc = check_lds(c, L);
+  if (rc != NSGC_OK) return rc;
+  const size_t pbytes = hp.plan_bytes();
+  const WsLayout lay = hp.layout();
+  if ((rc = ensure_device(&sl->plan_dev, &sl->plan_cap, pbytes, s)) != NSGC_OK) return rc;
+  if ((rc = ensure_device(&sl->ws, &sl->ws_cap, lay.total, s)) != NSGC_OK) return rc;
+  int k = 0;
+  if ((rc = take_stage(sl, pbytes, s, &k)) != NSGC_OK) return rc;
+  hp.serialize(sl->stage[k], reinterpret_cast<uint64_t>(sl->plan_dev),
+               reinterpret_cast<uint64_t>(sl->ws), src, dst, out);
+  NSGC_HIP(hipMemcpyAsync(sl->plan_dev, sl->stage[k], pbytes, hipMemcpyHostToDevice, s));
+  NSGC_HIP(hipEventRecord(sl->ev[k], s));
+  sl->ev_used[k] = true;
+  return enqueue_kernels(hp, reinterpret_cast<const nsgc_dev_plan*>(sl->plan_dev), L,
+                         hp.tile_log2, s, false);
+}
+
+// Upper bound of the workspace for any batch within the limits.
+size_t workspace_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune& t) {
+  const uint64_t P = uint64_t(std::max<int64_t>(max_packets, 0));
+  const uint64_t W = uint64_t(std::max<int64_t>(max_windows, 1));
+  int lt = 1 << 30, rt = 1 << 30;
+  for (int k = 0; k <= 32; ++k) {
+    lt = std::min(lt, t.cls[k].link_target);
+    rt = std::min(rt, std::min(t.cls[k].row_target, t.cls[k].col_target));
+  }
+  const uint64_t M = uint64_t(1) << t.max_buckets_log2;
+  const uint64_t T = uint64_t(1) << t.tile_log2;
+  const uint64_t bmax = std::min<uint64_t>(M, 2 * P / uint64_t(lt) + 1);
+  const uint64_t rmax = std::min<uint64_t>(M, 2 * P / uint64_t(rt) + 1);
+  const uint64_t tilemeta = (P / T + W) * (bmax + 2);
+  const uint64_t lbmeta = (std::min<uint64_t>(bmax * W, 2 * P / uint64_t(lt) + W)) * (2 * rmax + 3);
+  return size_t(P * 24 + (tilemeta + lbmeta + W) * 4 + 8 * 256);
+}
+
+size_t plan_bound(int64_t max_windows) {
+  const size_t W = size_t(std::max<int64_t>(max_windows, 1));
+  return 1024 + W * (sizeof(nsgc_small_desc) + sizeof(nsgc_win_desc) + 12) + 1024;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* nsgc_status_string(int status) {
+  switch (status) {
+    case NSGC_OK: return "ok";
+    case NSGC_ERR_INVALID_ARG: return "invalid argument";
+    case NSGC_ERR_BAD_OFFSETS: return "bad window offsets (negative, decreasing, or a window of 2^32 or more packets)";
+    case NSGC_ERR_NO_MEMORY: return "device workspace allocation failed";
+    case NSGC_ERR_HIP: return "HIP runtime error";
+    case NSGC_ERR_INTERNAL: return "internal error";
+    case NSGC_ERR_CAPTURING: return "allocation needed while the stream is being captured";
+    default: return "unknown status";
+  }
+}
+
+int nsgc_last_hip_error(void) { return t_last_hip_error; }
+
+int nsgc_window_stats(const uint32_t* src, const uint32_t* dst, const int64_t* window_offsets,
+                      int64_t num_windows, nsgc_stats* out_stats, void* stream) {
+  int rc = validate_common(src, dst, window_offsets, num_windows, out_stats);
+  if (rc != NSGC_OK || num_windows == 0) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  const nsgc_tune t = current_tune();
+  HostPlan hp;
+  if ((rc = make_plan(window_offsets, num_windows, t, &hp)) != NSGC_OK) return rc;
+  DevCtx* c = nullptr;
+  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  Slot* sl = nullptr;
+  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
+  return run_plan(c, sl, hp, t, src, dst, out_stats, s);
+}
+
+int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
+                            const int64_t* window_offsets, int64_t num_windows,
+                            nsgc_stats* out_stats, void* stream) {
+  int rc = validate_common(src, dst, window_offsets, num_windows, out_stats);
+  if (rc != NSGC_OK || num_windows == 0) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  const nsgc_tune t = current_tune();
+  DevCtx* c = nullptr;
+  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  Slot* sl = nullptr;
+  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
+  const Launch L = launch_params(c, t);
+  if ((rc = check_lds(c, L)) != NSGC_OK) return rc;
+
+  // One plan per window, all uploaded with one copy; the windows then run one
+  // launch sequence each, in order, sharing one workspace.
+  std::vector<HostPlan> plans(static_cast<size_t>(num_windows));
+  std::vector<size_t> at(static_cast<size_t>(num_windows));
+  size_t pbytes = 0, wsmax = 0;
+  for (int64_t w = 0; w < num_windows; ++w) {
+    if ((rc = make_plan(window_offsets + w, 1, t, &plans[size_t(w)])) != NSGC_OK) return rc;
+    at[size_t(w)] = pbytes;
+    pbytes += (plans[size_t(w)].plan_bytes() + 255) / 256 * 256;
+    wsmax = std::max(wsmax, plans[size_t(w)].layout().total);
+  }
+  if ((rc = ensure_device(&sl->plan_dev, &sl->plan_cap, pbytes, s)) != NSGC_OK) return rc;
+  if ((rc = ensure_device(&sl->ws, &sl->ws_cap, wsmax, s)) != NSGC_OK) return rc;
+  int k = 0;
+  if ((rc = take_stage(sl, pbytes, s, &k)) != NSGC_OK) return rc;
+  for (int64_t w = 0; w < num_windows; ++w)
+    plans[size_t(w)].serialize(sl->stage[k] + at[size_t(w)],
+                               reinterpret_cast<uint64_t>(sl->plan_dev + at[size_t(w)]),
+                               reinterpret_cast<uint64_t>(sl->ws), src, dst, out_stats + w);
+  NSGC_HIP(hipMemcpyAsync(sl->plan_dev, sl->stage[k], pbytes, hipMemcpyHostToDevice, s));
+  NSGC_HIP(hipEventRecord(sl->ev[k], s));
+  sl->ev_used[k] = true;
+  for (int64_t w = 0; w < num_windows; ++w) {
+    rc = enqueue_kernels(plans[size_t(w)],
+                         reinterpret_cast<const nsgc_dev_plan*>(sl->plan_dev + at[size_t(w)]), L,
+                         plans[size_t(w)].tile_log2, s, false);
+    if (rc != NSGC_OK) return rc;
+  }
+  return NSGC_OK;
+}
+
+int nsgc_reserve(int64_t max_packets, int64_t max_windows, void* stream) {
+  if (max_packets < 0 || max_windows < 0) return NSGC_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  const nsgc_tune t = current_tune();
+  DevCtx* c = nullptr;
+  int rc;
+  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  Slot* sl = nullptr;
+  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
+  if ((rc = ensure_device(&sl->plan_dev, &sl->plan_cap, plan_bound(max_windows), s)) != NSGC_OK)
+    return rc;
+  if ((rc = ensure_device(&sl->ws, &sl->ws_cap, workspace_bound(max_packets, max_windows, t), s)) !=
+      NSGC_OK)
+    return rc;
+  for (int k = 0; k < kStages; ++k) {
+    int idx = 0;
+    if ((rc = take_stage(sl, plan_bound(max_windows), s, &idx)) != NSGC_OK) return rc;
+  }
+  return NSGC_OK;
+}
+
+int nsgc_release(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  NSGC_HIP(hipGetDevice(&dev));
+  auto it = g_devs.find(dev);
+  if (it == g_devs.end()) return NSGC_OK;
+  NSGC_HIP(hipDeviceSynchronize());
+  for (auto& kv : it->second->slots) {
+    Slot* sl = kv.second;
+    if (sl->plan_dev) (void)hipFree(sl->plan_dev);
+    if (sl->ws) (void)hipFree(sl->ws);
+    for (int k = 0; k < kStages; ++k) {
+      if (sl->stage[k]) (void)hipHostFree(sl->stage[k]);
+      if (sl->ev[k]) (void)hipEventDestroy(sl->ev[k]);
+    }
+    delete sl;
+  }
+  it->second->slots.clear();
+  return NSGC_OK;
+}
+
+int nsgc_default_tune(nsgc_tune* out) {
+  if (!out) return NSGC_ERR_INVALID_ARG;
+  default_tune(out);
+  return NSGC_OK;
+}
+
+int nsgc_get_tune(nsgc_tune* out) {
+  if (!out) return NSGC_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  *out = current_tune();
+  return NSGC_OK;
+}
+
+int nsgc_set_tune(const nsgc_tune* tune) {
+  if (!tune) return NSGC_ERR_INVALID_ARG;
+  const int rc = check_tune(*tune);
+  if (rc != NSGC_OK) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_tune = *tune;
+  g_tune_set = true;
+  return NSGC_OK;
+}
+
+int nsgc_plan_inspect(const int64_t* window_offsets, int64_t num_windows, int32_t* tier,
+                      int32_t* log2_link_buckets, int32_t* log2_row_buckets,
+                      int32_t* log2_col_buckets, int64_t* tiles, int64_t* workspace_bytes) {
+  if (num_windows < 0) return NSGC_ERR_INVALID_ARG;
+  if (num_windows > 0 && !window_offsets) return NSGC_ERR_INVALID_ARG;
+  if (num_windows > 0) {
+    const int rc = validate_offsets(window_offsets, num_windows);
+    if (rc != NSGC_OK) return rc;
+  }
+  nsgc_tune t;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    t = current_tune();
+  }
+  HostPlan hp;
+  const int rc = make_plan(window_offsets, num_windows, t, &hp);
+  if (rc != NSGC_OK) return rc;
+  size_t m = 0;
+  for (int64_t w = 0; w < num_windows; ++w) {
+    if (tier) tier[w] = hp.tier[size_t(w)];
+    const bool part = hp.tier[size_t(w)] == 2;
+    const nsgc_win_desc* d = part ? &hp.win[m] : nullptr;
+    if (log2_link_buckets) log2_link_buckets[w] = d ? d->logB : -1;
+    if (log2_row_buckets) log2_row_buckets[w] = d ? d->logR : -1;
+    if (log2_col_buckets) log2_col_buckets[w] = d ? d->logC : -1;
+    if (tiles) tiles[w] = d ? int64_t(d->ntiles) : 0;
+    if (part) ++m;
+  }
+  if (workspace_bytes) *workspace_bytes = int64_t(hp.layout().total);
+  return NSGC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graph form.
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+struct nsgc_graph {
+  int device = 0;
+  nsgc_tune tune;
+  Launch L;
+  int64_t max_packets = 0, max_windows = 0;
+  hipStream_t capture = nullptr;
+  // two instances so the host can plan batch i+1 while batch i runs
+  struct Inst {
+    char* plan_dev = nullptr;
+    size_t plan_cap = 0;
+    char* stage = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool used = false;
+  } inst[2];
+  int next = 0;
+  char* ws = nullptr;
+  size_t ws_cap = 0;
+};
+
+namespace {
+
+int capture_instance(nsgc_graph* g, nsgc_graph::Inst& in) {
+  NSGC_HIP(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipMemcpyAsync(in.plan_dev, in.stage, in.plan_cap, hipMemcpyHostToDevice,
+                                g->capture);
+  HostPlan empty;
+  int rc = NSGC_OK;
+  if (e == hipSuccess) {
+    rc = enqueue_kernels(empty, reinterpret_cast<const nsgc_dev_plan*>(in.plan_dev), g->L,
+                         uint32_t(g->tune.tile_log2), g->capture, true);
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(g->capture, &graph);
+  if (e != hipSuccess) return hip_fail(e);
+  if (rc != NSGC_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e2 != hipSuccess) return hip_fail(e2);
+  in.graph = graph;
+  NSGC_HIP(hipGraphInstantiate(&in.exec, graph, nullptr, nullptr, 0));
+  return NSGC_OK;
+}
+
+void destroy_graph(nsgc_graph* g) {
+  for (auto& in : g->inst) {
+    if (in.done) (void)hipEventSynchronize(in.done);
+    if (in.exec) (void)hipGraphExecDestroy(in.exec);
+    if (in.graph) (void)hipGraphDestroy(in.graph);
+    if (in.plan_dev) (void)hipFree(in.plan_dev);
+    if (in.stage) (void)hipHostFree(in.stage);
+    if (in.done) (void)hipEventDestroy(in.done);
+  }
+  if (g->ws) (void)hipFree(g->ws);
+  if (g->capture) (void)hipStreamDestroy(g->capture);
+  delete g;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nsgc_graph_create(int64_t max_packets, int64_t max_windows, nsgc_graph** out) {
+  if (!out || max_packets < 0 || max_windows < 1) return NSGC_ERR_INVALID_ARG;
+  *out = nullptr;
+  std::lock_guard<std::mutex> lock(g_mu);
+  DevCtx* c = nullptr;
+  int rc;
+  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
+  nsgc_graph* g = new nsgc_graph;
+  g->device = c->device;
+  g->tune = current_tune();
+  g->L = launch_params(c, g->tune);
+  g->max_packets = max_packets;
+  g->max_windows = max_windows;
+  if ((rc = check_lds(c, g->L)) != NSGC_OK) {
+    destroy_graph(g);
+    return rc;
+  }
+  hipError_t e = hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    destroy_graph(g);
+    return hip_fail(e);
+  }
+  const size_t pb = plan_bound(max_windows);
+  for (auto& in : g->inst) {
+    void* p = nullptr;
+    if ((e = hipMalloc(&p, pb)) != hipSuccess) { destroy_graph(g); return NSGC_ERR_NO_MEMORY; }
+    in.plan_dev = static_cast<char*>(p);
+    in.plan_cap = pb;
+    if ((e = hipHostMalloc(&p, pb, hipHostMallocDefault)) != hipSuccess) {
+      destroy_graph(g);
+      return hip_fail(e);
+    }
+    in.stage = static_cast<char*>(p);
+    std::memset(in.stage, 0, pb);
+    if ((e = hipEventCreateWithFlags(&in.done, hipEventDisableTiming)) != hipSuccess) {
+      destroy_graph(g);
+      return hip_fail(e);
+    }
+    if ((rc = capture_instance(g, in)) != NSGC_OK) {
+      destroy_graph(g);
+      return rc;
+    }
+  }
+  if ((rc = ensure_device(&g->ws, &g->ws_cap, workspace_bound(max_packets, max_windows, g->tune),
+                          g->capture)) != NSGC_OK) {
+    destroy_graph(g);
+    return rc;
+  }
+  *out = g;
+  return NSGC_OK;
+}
+
+int nsgc_graph_launch(nsgc_graph* g, const uint32_t* src, const uint32_t* dst,
+                      const int64_t* window_offsets, int64_t num_windows, nsgc_stats* out_stats,
+                      void* stream) {
+  if (!g) return NSGC_ERR_INVALID_ARG;
+  int rc = validate_common(src, dst, window_offsets, num_windows, out_stats);
+  if (rc != NSGC_OK || num_windows == 0) return rc;
+  if (num_windows > g->max_windows) return NSGC_ERR_INVALID_ARG;
+  if (window_offsets[num_windows] - window_offsets[0] > g->max_packets) return NSGC_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  NSGC_HIP(hipGetDevice(&dev));
+  if (dev != g->device) return NSGC_ERR_INVALID_ARG;
+  HostPlan hp;
+  if ((rc = make_plan(window_offsets, num_windows, g->tune, &hp)) != NSGC_OK) return rc;
+  if (hp.plan_bytes() > g->inst[0].plan_cap) return NSGC_ERR_INTERNAL;
+  const size_t need = hp.layout().total;
+  if (need > g->ws_cap) {
+    // wait for both instances before moving the shared workspace
+    for (auto& in : g->inst)
+      if (in.used) NSGC_HIP(hipEventSynchronize(in.done));
+    if ((rc = ensure_device(&g->ws, &g->ws_cap, need, s)) != NSGC_OK) return rc;
+  }
+  nsgc_graph::Inst& in = g->inst[g->next];
+  if (in.used) NSGC_HIP(hipEventSynchronize(in.done));
+  hp.serialize(in.stage, reinterpret_cast<uint64_t>(in.plan_dev), reinterpret_cast<uint64_t>(g->ws),
+               src, dst, out_stats);
+  NSGC_HIP(hipGraphLaunch(in.exec, s));
+  NSGC_HIP(hipEventRecord(in.done, s));
+  in.used = true;
+  g->next ^= 1;
+  return NSGC_OK;
+}
+
+int nsgc_graph_destroy(nsgc_graph* g) {
+  if (!g) return NSGC_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  destroy_graph(g);
+  return NSGC_OK;
+}
+
+}  // extern "C"

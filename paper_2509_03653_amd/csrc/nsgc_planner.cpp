@@ -1,0 +1,199 @@
+// Host planner (see nsgc_plan.h for the tiers and phases it lays out).
+#include "nsgc_planner.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+namespace nsgc {
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+int ceil_log2(uint64_t x) {
+  int k = 0;
+  while ((uint64_t(1) << k) < x) ++k;
+  return k;
+}
+
+void default_tune(nsgc_tune* t) {
+  std::memset(t, 0, sizeof(*t));
+  t->small_max = 1024;
+  t->tile_log2 = 13;
+  t->link_slots_log2 = 12;
+  t->rc_slots_log2 = 12;
+  t->blocks_per_cu = 2;
+  t->max_buckets_log2 = 10;
+  for (int k = 0; k <= 32; ++k) {
+    t->cls[k].link_target = 2048;
+    t->cls[k].row_target = 4096;
+    t->cls[k].col_target = 4096;
+  }
+}
+
+int check_tune(const nsgc_tune& t) {
+  if (t.small_max < 0 || t.small_max > 2048) return NSGC_ERR_INVALID_ARG;
+  if (t.tile_log2 < 11 || t.tile_log2 > 14) return NSGC_ERR_INVALID_ARG;
+  if (t.link_slots_log2 < 10 || t.link_slots_log2 > 13) return NSGC_ERR_INVALID_ARG;
+  if (t.rc_slots_log2 < 10 || t.rc_slots_log2 > 13) return NSGC_ERR_INVALID_ARG;
+  if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16) return NSGC_ERR_INVALID_ARG;
+  if (t.max_buckets_log2 < 0 || t.max_buckets_log2 > 12) return NSGC_ERR_INVALID_ARG;
+  for (int k = 0; k <= 32; ++k) {
+    const nsgc_tune_class& c = t.cls[k];
+    if (c.link_target < 64 || c.row_target < 64 || c.col_target < 64) return NSGC_ERR_INVALID_ARG;
+  }
+  return NSGC_OK;
+}
+
+int validate_offsets(const int64_t* offsets, int64_t num_windows) {
+  if (offsets[0] < 0) return NSGC_ERR_BAD_OFFSETS;
+  for (int64_t w = 0; w < num_windows; ++w) {
+    const int64_t n = offsets[w + 1] - offsets[w];
+    if (offsets[w + 1] < offsets[w]) return NSGC_ERR_BAD_OFFSETS;
+    if (n > int64_t(0xFFFFFFFFll)) return NSGC_ERR_BAD_OFFSETS;
+  }
+  return NSGC_OK;
+}
+
+int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune,
+              HostPlan* p) {
+  p->small.clear();
+  p->win.clear();
+  p->prefA.clear();
+  p->prefB.clear();
+  p->prefC.clear();
+  p->tier.assign(size_t(num_windows), 0);
+  p->ws_elems = p->tilemeta_words = p->lbmeta_words = 0;
+  p->tile_log2 = uint32_t(tune.tile_log2);
+  p->link_slots_log2 = uint32_t(tune.link_slots_log2);
+  p->rc_slots_log2 = uint32_t(tune.rc_slots_log2);
+  p->small_slots_log2 = uint32_t(std::max(ceil_log2(uint64_t(std::max(tune.small_max, 1)) * 2), 6));
+
+  const uint64_t tile = uint64_t(1) << tune.tile_log2;
+  uint64_t a = 0, b = 0, c = 0;
+  for (int64_t w = 0; w < num_windows; ++w) {
+    const uint64_t n = uint64_t(offsets[w + 1] - offsets[w]);
+    if (n <= uint64_t(tune.small_max)) {
+      nsgc_small_desc s;
+      s.in_begin = offsets[w];
+      s.n = uint32_t(n);
+      s.out_index = uint32_t(w);
+      p->small.push_back(s);
+      p->tier[size_t(w)] = n == 0 ? 0 : 1;
+      continue;
+    }
+    p->tier[size_t(w)] = 2;
+    int cls = 0;
+    while (cls < 32 && (uint64_t(1) << (cls + 1)) <= n) ++cls;
+    const nsgc_tune_class& tc = tune.cls[cls];
+    const int cap = tune.max_buckets_log2;
+    nsgc_win_desc d;
+    std::memset(&d, 0, sizeof d);
+    d.in_begin = offsets[w];
+    d.n = uint32_t(n);
+    d.out_index = uint32_t(w);
+    d.logB = uint8_t(std::min(ceil_log2((n + uint64_t(tc.link_target) - 1) / uint64_t(tc.link_target)), cap));
+    d.logR = uint8_t(std::min(ceil_log2((n + uint64_t(tc.row_target) - 1) / uint64_t(tc.row_target)), cap));
+    d.logC = uint8_t(std::min(ceil_log2((n + uint64_t(tc.col_target) - 1) / uint64_t(tc.col_target)), cap));
+    d.ntiles = uint32_t((n + tile - 1) / tile);
+    d.counter = uint32_t(p->win.size());
+    d.ws = p->ws_elems;
+    d.tilemeta = p->tilemeta_words;
+    d.lbmeta = p->lbmeta_words;
+    const uint64_t B = uint64_t(1) << d.logB, R = uint64_t(1) << d.logR, C = uint64_t(1) << d.logC;
+    p->ws_elems += int64_t(n);
+    p->tilemeta_words += int64_t(uint64_t(d.ntiles) * (B + 1));
+    p->lbmeta_words += int64_t(B * (R + C + 3));
+    p->prefA.push_back(uint32_t(a));
+    p->prefB.push_back(uint32_t(b));
+    p->prefC.push_back(uint32_t(c));
+    a += d.ntiles;
+    b += B;
+    c += R + C;
+    if (a > 0xFFFFFFFFull || b > 0xFFFFFFFFull || c > 0xFFFFFFFFull) return NSGC_ERR_INVALID_ARG;
+    p->win.push_back(d);
+  }
+  p->prefA.push_back(uint32_t(a));
+  p->prefB.push_back(uint32_t(b));
+  p->prefC.push_back(uint32_t(c));
+  p->itemsA = uint32_t(a);
+  p->itemsB = uint32_t(b);
+  p->itemsC = uint32_t(c);
+  return NSGC_OK;
+}
+
+WsLayout HostPlan::layout() const {
+  WsLayout L;
+  const size_t e = size_t(ws_elems) * 8;
+  size_t o = 0;
+  L.keys = o;      o = align_up(o + e, 256);
+  L.emit_row = o;  o = align_up(o + e, 256);
+  L.emit_col = o;  o = align_up(o + e, 256);
+  L.tilemeta = o;  o = align_up(o + size_t(tilemeta_words) * 4, 256);
+  L.lbmeta = o;    o = align_up(o + size_t(lbmeta_words) * 4, 256);
+  L.counters = o;  o = align_up(o + win.size() * 4, 256);
+  L.total = std::max<size_t>(o, 256);
+  return L;
+}
+
+namespace {
+struct PlanOffsets {
+  size_t small, win, prefA, prefB, prefC, total;
+};
+PlanOffsets plan_offsets(size_t ns, size_t nm) {
+  PlanOffsets o;
+  size_t x = align_up(sizeof(nsgc_dev_plan), 64);
+  o.small = x; x = align_up(x + ns * sizeof(nsgc_small_desc), 64);
+  o.win = x;   x = align_up(x + nm * sizeof(nsgc_win_desc), 64);
+  o.prefA = x; x = align_up(x + (nm + 1) * 4, 64);
+  o.prefB = x; x = align_up(x + (nm + 1) * 4, 64);
+  o.prefC = x; x = align_up(x + (nm + 1) * 4, 64);
+  o.total = x;
+  return o;
+}
+}  // namespace
+
+size_t HostPlan::plan_bytes() const { return plan_offsets(small.size(), win.size()).total; }
+
+void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const uint32_t* src,
+                         const uint32_t* dst, void* out) const {
+  const PlanOffsets o = plan_offsets(small.size(), win.size());
+  const WsLayout L = layout();
+  char* base = static_cast<char*>(buf);
+  std::memset(base, 0, align_up(sizeof(nsgc_dev_plan), 64));
+  nsgc_dev_plan h;
+  std::memset(&h, 0, sizeof h);
+  h.src = src;
+  h.dst = dst;
+  h.out = static_cast<unsigned long long*>(out);
+  h.keys = reinterpret_cast<unsigned long long*>(dev_ws + L.keys);
+  h.emit_row = reinterpret_cast<unsigned long long*>(dev_ws + L.emit_row);
+  h.emit_col = reinterpret_cast<unsigned long long*>(dev_ws + L.emit_col);
+  h.tilemeta = reinterpret_cast<uint32_t*>(dev_ws + L.tilemeta);
+  h.lbmeta = reinterpret_cast<uint32_t*>(dev_ws + L.lbmeta);
+  h.counters = reinterpret_cast<uint32_t*>(dev_ws + L.counters);
+  h.small = reinterpret_cast<const nsgc_small_desc*>(dev_plan + o.small);
+  h.win = reinterpret_cast<const nsgc_win_desc*>(dev_plan + o.win);
+  h.prefA = reinterpret_cast<const uint32_t*>(dev_plan + o.prefA);
+  h.prefB = reinterpret_cast<const uint32_t*>(dev_plan + o.prefB);
+  h.prefC = reinterpret_cast<const uint32_t*>(dev_plan + o.prefC);
+  h.num_small = uint32_t(small.size());
+  h.num_part = uint32_t(win.size());
+  h.itemsA = itemsA;
+  h.itemsB = itemsB;
+  h.itemsC = itemsC;
+  h.tile_log2 = tile_log2;
+  h.link_slots_log2 = link_slots_log2;
+  h.rc_slots_log2 = rc_slots_log2;
+  h.small_slots_log2 = small_slots_log2;
+  std::memcpy(base, &h, sizeof h);
+  if (!small.empty()) std::memcpy(base + o.small, small.data(), small.size() * sizeof(nsgc_small_desc));
+  if (!win.empty()) std::memcpy(base + o.win, win.data(), win.size() * sizeof(nsgc_win_desc));
+  std::memcpy(base + o.prefA, prefA.data(), prefA.size() * 4);
+  std::memcpy(base + o.prefB, prefB.data(), prefB.size() * 4);
+  std::memcpy(base + o.prefC, prefC.data(), prefC.size() * 4);
+}
+
+}  // namespace nsgc

@@ -1,0 +1,119 @@
+"""Host-only checks of the C ABI: exports, argument validation, planner.
+
+No device work happens here: invalid arguments are rejected before any HIP
+call, and nsgc_plan_inspect is pure host code.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2509_03653_amd as nsgc
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "nsgc.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nsgc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert header_functions() == sorted(nsgc.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = nsgc.library()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.check_output(["nm", "-D", "--defined-only", nsgc.LIB_PATH]).decode()
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    for name in header_functions():
+        assert name in exported, name
+
+
+def test_status_strings():
+    lib = nsgc.library()
+    for code in range(-6, 1):
+        assert lib.nsgc_status_string(code)
+    assert lib.nsgc_status_string(-99) == b"unknown status"
+
+
+def _call(fn, src, dst, off, w, out):
+    return fn(ctypes.c_void_p(src), ctypes.c_void_p(dst),
+              ctypes.c_void_p(off.ctypes.data if off is not None else 0), w,
+              ctypes.c_void_p(out), ctypes.c_void_p(0))
+
+
+@pytest.mark.parametrize("entry", ["nsgc_window_stats", "nsgc_window_stats_plain"])
+def test_invalid_arguments_rejected_before_any_device_work(entry):
+    fn = getattr(nsgc.library(), entry)
+    off = np.array([0, 4, 8], np.int64)
+    fake = 0x1000   # never dereferenced: validation fails first
+    assert _call(fn, fake, fake, off, -1, fake) == -1           # negative count
+    assert _call(fn, fake, fake, None, 2, fake) == -1           # no offsets
+    assert _call(fn, fake, fake, off, 2, 0) == -1               # no output
+    assert _call(fn, fake, fake, off, 2, fake + 4) == -1        # misaligned output
+    assert _call(fn, 0, fake, off, 2, fake) == -1               # packets but no src
+    assert _call(fn, 0, 0, off, 0, 0) == 0                      # zero windows: no-op
+    bad = np.array([0, 4, 3], np.int64)
+    assert _call(fn, fake, fake, bad, 2, fake) == -2            # decreasing
+    neg = np.array([-1, 4], np.int64)
+    assert _call(fn, fake, fake, neg, 1, fake) == -2            # negative
+    huge = np.array([0, 1 << 32], np.int64)
+    assert _call(fn, fake, fake, huge, 1, fake) == -2           # window of 2^32 packets
+
+
+def test_tune_roundtrip_and_validation():
+    t = nsgc.default_tune()
+    d = t.to_dict()
+    assert d["small_max"] >= 0 and 11 <= d["tile_log2"] <= 14
+    t2 = nsgc.Tune.from_dict(d)
+    assert t2.to_dict() == d
+    bad = nsgc.Tune.from_dict(dict(d, tile_log2=9))
+    with pytest.raises(nsgc.NsgcError):
+        nsgc.set_tune(bad)
+    assert nsgc.get_tune().to_dict() == d
+
+
+def test_plan_tiers_and_cutover():
+    small_max = nsgc.get_tune().small_max
+    sizes = [0, 1, small_max, small_max + 1, 1 << 17, 1 << 23]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    p = nsgc.plan_inspect(off)
+    assert list(p["tier"]) == [0, 1, 1, 2, 2, 2]
+    assert list(p["tiles"][:3]) == [0, 0, 0]
+    t = nsgc.get_tune()
+    tile = 1 << t.tile_log2
+    for i in (3, 4, 5):
+        assert p["tiles"][i] == -(-sizes[i] // tile)
+        cls = int(np.floor(np.log2(sizes[i])))
+        lt = t.cls[cls].link_target
+        want = min(int(np.ceil(np.log2(max(1, -(-sizes[i] // lt))))), t.max_buckets_log2)
+        assert p["log2_link_buckets"][i] == want
+    assert p["workspace_bytes"] >= 24 * (sum(sizes[3:]))
+
+
+def test_plan_rejects_bad_offsets():
+    with pytest.raises(nsgc.NsgcError):
+        nsgc.plan_inspect(np.array([0, 5, 2], np.int64))
+    p = nsgc.plan_inspect(np.array([7], np.int64))
+    assert p["tier"].size == 0
+
+
+def test_plan_workspace_grows_with_packets():
+    a = nsgc.plan_inspect(np.array([0, 1 << 16], np.int64))["workspace_bytes"]
+    b = nsgc.plan_inspect(np.array([0, 1 << 20], np.int64))["workspace_bytes"]
+    assert b > a >= 24 * (1 << 16)
+
+
+def test_no_cpu_path():
+    torch = pytest.importorskip("torch")
+    s = torch.zeros(4, dtype=torch.int32)
+    with pytest.raises(ValueError):
+        nsgc.window_stats(s, s, [0, 4])

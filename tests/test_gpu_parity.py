@@ -1,0 +1,208 @@
+"""GPU parity: the HIP library against the CPU oracle, bit-exact on all nine
+statistics (they are exact integer counts; the bar is equality).
+
+Sizes here let the oracle finish in seconds while still spanning several
+partition tiles, several link/row/column buckets and ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2509_03653_amd as nsgc
+import synth
+from conftest import load_golden_batch, load_golden_windows
+from gpu_util import assert_same, gpu_stats, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _default_tune():
+    nsgc.set_tune(nsgc.default_tune())
+    yield
+    nsgc.set_tune(nsgc.default_tune())
+
+
+def check(src, dst, off, what, forms=("batched",)):
+    want = oracle.window_stats(src, dst, off, threads=8)
+    for form in forms:
+        say(f"[gpu] {what} form={form} windows={len(off) - 1} packets={int(off[-1] - off[0])}")
+        assert_same(gpu_stats(src, dst, off, form), want, f"{what}/{form}")
+    return want
+
+
+def test_golden_windows_each_form():
+    for name, (s, d, e) in sorted(load_golden_windows().items()):
+        off = np.array([0, s.size], np.int64)
+        for form in ("batched", "plain", "graph"):
+            say(f"[gpu] golden {name} {form}")
+            assert_same(gpu_stats(s, d, off, form), e[None, :], f"golden {name} {form}")
+
+
+def test_golden_batch():
+    src, dst, off, expected = load_golden_batch()
+    for form in ("batched", "plain", "graph"):
+        assert_same(gpu_stats(src, dst, off, form), expected, f"golden batch {form}")
+
+
+def test_golden_windows_through_partitioned_tier():
+    # the same hand-worked windows, forced through phases A-C (small tier off)
+    t = nsgc.default_tune()
+    t.small_max = 0
+    nsgc.set_tune(t)
+    for name, (s, d, e) in sorted(load_golden_windows().items()):
+        off = np.array([0, s.size], np.int64)
+        assert_same(gpu_stats(s, d, off), e[None, :], f"golden {name} partitioned")
+    src, dst, off, expected = load_golden_batch()
+    assert_same(gpu_stats(src, dst, off), expected, "golden batch partitioned")
+
+
+def test_random_tiny_windows_many_alphabets():
+    rng = np.random.default_rng(7)
+    sizes = rng.integers(0, 300, 600)
+    sizes[::50] = 0
+    off = synth.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    alph = rng.choice([1, 2, 3, 7, 40, 1000, 1 << 32], size=600)
+    src = np.zeros(n, np.uint32)
+    dst = np.zeros(n, np.uint32)
+    for w in range(600):
+        a, b = off[w], off[w + 1]
+        src[a:b] = rng.integers(0, alph[w], b - a, dtype=np.uint64).astype(np.uint32)
+        dst[a:b] = rng.integers(0, alph[w], b - a, dtype=np.uint64).astype(np.uint32)
+        if w % 9 == 0:
+            dst[a:b] = src[a:b]                   # self-loops
+        if w % 13 == 0:
+            src[a:b] = 0xFFFFFFFF                 # extreme addresses
+            dst[a:(a + b) // 2] = 0xFFFFFFFF      # the packed key ~0 is legal
+    check(src, dst, off, "tiny windows", forms=("batched", "plain", "graph"))
+
+
+def test_size_boundaries():
+    t = nsgc.get_tune()
+    sm, tile = t.small_max, 1 << t.tile_log2
+    sizes = [0, 1, 2, 63, 64, 65, sm - 1, sm, sm + 1, tile - 1, tile, tile + 1,
+             2 * tile + 7, 5 * tile - 3, 3 * 2048 + 1]
+    off = synth.offsets_from_sizes(sizes)
+    rng = np.random.default_rng(11)
+    n = int(off[-1])
+    src = rng.integers(0, 300, n).astype(np.uint32)
+    dst = rng.integers(0, 5000, n).astype(np.uint32)
+    check(src, dst, off, "size boundaries", forms=("batched", "plain", "graph"))
+
+
+def test_heavy_contention_windows():
+    n = 40000
+    off = synth.offsets_from_sizes([n, n, n, n, 700])
+    src = np.zeros(int(off[-1]), np.uint32)
+    dst = np.zeros(int(off[-1]), np.uint32)
+    # w0: all packets identical
+    src[0:n], dst[0:n] = 5, 9
+    # w1: one source to many destinations (a star) plus repeats
+    src[n:2 * n] = 77
+    dst[n:2 * n] = np.arange(n) % 12345
+    # w2: all packets are the key 0xFFFFFFFF_FFFFFFFF
+    src[2 * n:3 * n] = 0xFFFFFFFF
+    dst[2 * n:3 * n] = 0xFFFFFFFF
+    # w3: address 0 and self-loops mixed
+    rng = np.random.default_rng(3)
+    x = rng.integers(0, 3, n).astype(np.uint32)
+    src[3 * n:4 * n] = x
+    dst[3 * n:4 * n] = np.where(rng.random(n) < 0.5, x, 0).astype(np.uint32)
+    # w4: small window of identical packets
+    src[4 * n:], dst[4 * n:] = 1, 1
+    check(src, dst, off, "contention", forms=("batched", "plain"))
+
+
+@pytest.mark.parametrize("maker", ["uniform_single", "zipf_batch", "skewed_large",
+                                   "uneven_batch", "serving_stream"])
+def test_workloads_scaled_down(maker):
+    fn = synth.WORKLOADS[maker]
+    if maker in ("uneven_batch", "serving_stream"):
+        wl = fn(seed=2, num_windows=48, lo_log2=6, hi_log2=17)
+    elif maker == "uniform_single":
+        wl = fn(seed=2, num_windows=2, log2_window=17)
+    else:
+        wl = fn(seed=2, num_windows=6, log2_window=16)
+    src, dst = wl.generate()
+    check(src, dst, wl.offsets, maker, forms=("batched", "plain"))
+
+
+TUNES = {
+    "tiny_tables_forced_sweeps": dict(link_slots_log2=10, rc_slots_log2=10,
+                                      cls=[[65536, 65536, 65536]] * 33),
+    "small_tier_off": dict(small_max=0),
+    "small_tier_max": dict(small_max=2048),
+    "tile_2k": dict(tile_log2=11),
+    "tile_16k": dict(tile_log2=14),
+    "one_bucket": dict(max_buckets_log2=0),
+    "many_buckets": dict(cls=[[64, 64, 64]] * 33, max_buckets_log2=12),
+    "big_tables": dict(link_slots_log2=13, rc_slots_log2=13, blocks_per_cu=1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(TUNES))
+def test_every_tuning_gives_identical_results(name):
+    wl = synth.zipf_batch(seed=4, num_windows=5, log2_window=15)
+    src, dst = wl.generate()
+    sizes = [0, 1, 900, 3000, 20000, 1 << 15, 77777]
+    off = synth.offsets_from_sizes(sizes)
+    s2, d2 = synth.fill(off, 9, wl.src_dist, wl.dst_dist)
+    base = nsgc.default_tune().to_dict()
+    base.update(TUNES[name])
+    nsgc.set_tune(nsgc.Tune.from_dict(base))
+    check(src, dst, wl.offsets, f"tune {name} zipf")
+    check(s2, d2, off, f"tune {name} mixed sizes", forms=("batched", "plain"))
+
+
+def test_repeated_runs_identical_and_nonzero_first_offset():
+    wl = synth.uneven_batch(seed=5, num_windows=30, lo_log2=8, hi_log2=16)
+    src, dst = wl.generate()
+    off = wl.offsets + 0
+    # drop the first 123 packets from window 0 so offsets[0] is non-zero
+    off[0] = 123
+    want = oracle.window_stats(src, dst, off, threads=8)
+    first = gpu_stats(src, dst, off)
+    assert_same(first, want, "offset start")
+    for _ in range(4):
+        assert_same(gpu_stats(src, dst, off), first, "repeat")
+
+
+def test_window_alone_equals_window_in_batch():
+    wl = synth.uneven_batch(seed=6, num_windows=20, lo_log2=8, hi_log2=16)
+    src, dst = wl.generate()
+    batch = gpu_stats(src, dst, wl.offsets)
+    for w in (0, 7, 19):
+        a, b = int(wl.offsets[w]), int(wl.offsets[w + 1])
+        alone = gpu_stats(src[a:b], dst[a:b], np.array([0, b - a], np.int64))
+        assert_same(alone[0:1], batch[w:w + 1], f"alone w{w}")
+
+
+def test_graph_reuse_with_different_batches():
+    import torch
+    g = nsgc.Graph(1 << 18, 64)
+    try:
+        for seed, nw in ((1, 40), (2, 3), (3, 64), (4, 1)):
+            wl = synth.uneven_batch(seed=seed, num_windows=nw, lo_log2=4, hi_log2=12)
+            src, dst = wl.generate()
+            want = oracle.window_stats(src, dst, wl.offsets)
+            got = gpu_stats(src, dst, wl.offsets, "graph", graph=g)
+            assert_same(got, want, f"graph reuse seed {seed}")
+        torch.cuda.synchronize()
+    finally:
+        g.close()
+
+
+def test_stream_argument_and_out_reuse():
+    import torch
+    wl = synth.zipf_batch(seed=8, num_windows=3, log2_window=14)
+    src, dst = wl.generate()
+    want = oracle.window_stats(src, dst, wl.offsets)
+    s = torch.from_numpy(src.view(np.int32)).cuda()
+    d = torch.from_numpy(dst.view(np.int32)).cuda()
+    out = torch.full((3, 9), -1, dtype=torch.int64, device="cuda")
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    nsgc.window_stats(s, d, wl.offsets, out=out, stream=st)
+    st.synchronize()
+    assert_same(out.cpu().numpy().view(np.uint64), want, "side stream")
