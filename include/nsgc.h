@@ -96,6 +96,18 @@ int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
                             const int64_t* window_offsets, int64_t num_windows,
                             nsgc_stats* out_stats, void* stream);
 
+/*
+ * Measurement form: the batched form with HIP events recorded on `stream`
+ * around each kernel launch.  Waits for the work to finish and writes the
+ * elapsed milliseconds of the four launches to phase_ms[0..3]: small-window
+ * kernel, partition, link aggregation, row/column aggregation (0 for a phase
+ * with no work).  Same arguments and results as nsgc_window_stats otherwise;
+ * phase_ms is a host array of 4 floats.  Not usable under stream capture.
+ */
+int nsgc_window_stats_timed(const uint32_t* src, const uint32_t* dst,
+                            const int64_t* window_offsets, int64_t num_windows,
+                            nsgc_stats* out_stats, void* stream, float* phase_ms);
+
 /* Human-readable text for a status code (static storage, never NULL). */
 const char* nsgc_status_string(int status);
 
@@ -128,7 +140,7 @@ typedef struct nsgc_tune {
   int32_t small_max;        /* windows with <= small_max packets run entirely in
                                LDS, one workgroup each (0..2048) */
   int32_t tile_log2;        /* partition tile: 2^tile_log2 packets (11..14) */
-  int32_t link_slots_log2;  /* LDS link table: 2^k slots (10..13) */
+  int32_t link_slots_log2;  /* LDS link table: 2^k slots (10..12) */
   int32_t rc_slots_log2;    /* LDS row/column table: 2^k slots (10..13) */
   int32_t blocks_per_cu;    /* persistent grid: workgroups per compute unit (1..16) */
   int32_t max_buckets_log2; /* cap on link/row/column buckets per window (0..12) */

@@ -48,6 +48,7 @@ STATUS = {
 EXPORTS = (
     "nsgc_window_stats",
     "nsgc_window_stats_plain",
+    "nsgc_window_stats_timed",
     "nsgc_status_string",
     "nsgc_last_hip_error",
     "nsgc_reserve",
@@ -129,6 +130,8 @@ def _lib():
         lib.nsgc_window_stats.restype = i32
         lib.nsgc_window_stats_plain.argtypes = [vp, vp, vp, i64, vp, vp]
         lib.nsgc_window_stats_plain.restype = i32
+        lib.nsgc_window_stats_timed.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        lib.nsgc_window_stats_timed.restype = i32
         lib.nsgc_status_string.argtypes = [i32]
         lib.nsgc_status_string.restype = ctypes.c_char_p
         lib.nsgc_last_hip_error.argtypes = []
@@ -223,6 +226,18 @@ def window_stats_plain(src, dst, offsets, out=None, stream=None):
     """Plain form (``nsgc_window_stats_plain``): one launch sequence per window."""
     return _run(_lib().nsgc_window_stats_plain, "nsgc_window_stats_plain", src, dst, offsets,
                 out, stream)
+
+
+PHASES = ("small", "partition", "links", "rowcol")
+
+
+def window_stats_timed(src, dst, offsets, out=None, stream=None):
+    """Measurement form (``nsgc_window_stats_timed``): returns ``(out, phase_ms)``
+    with the HIP-event duration of each of the four kernel launches."""
+    ms = (ctypes.c_float * 4)()
+    fn = lambda *a: _lib().nsgc_window_stats_timed(*a, ms)  # noqa: E731
+    out = _run(fn, "nsgc_window_stats_timed", src, dst, offsets, out, stream)
+    return out, dict(zip(PHASES, (float(x) for x in ms)))
 
 
 def reserve(max_packets: int, max_windows: int, stream=None):

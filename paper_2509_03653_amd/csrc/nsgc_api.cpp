@@ -18,13 +18,13 @@
 
 namespace nsgc {
 hipError_t launch_small(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
-hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t grid, size_t lds,
-                            hipStream_t s);
+hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t max_buckets,
+                            uint32_t grid, size_t lds, hipStream_t s);
 hipError_t launch_links(const nsgc_dev_plan* P, uint32_t max_buckets, uint32_t grid, size_t lds,
                         hipStream_t s);
 hipError_t launch_rowcol(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
 size_t lds_small_bytes(uint32_t slots_log2);
-size_t lds_part_bytes(uint32_t max_buckets);
+size_t lds_part_bytes(uint32_t max_buckets, uint32_t tile_log2);
 size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_buckets);
 size_t lds_rc_bytes(uint32_t slots_log2);
 hipError_t allow_large_lds(size_t bytes);
@@ -60,6 +60,7 @@ struct Slot {
   hipEvent_t ev[kStages] = {};
   bool ev_used[kStages] = {};
   int next = 0;
+  hipEvent_t phase_ev[5] = {};  // timing events of nsgc_window_stats_timed
 };
 
 struct DevCtx {
@@ -175,7 +176,7 @@ Launch launch_params(const DevCtx* c, const nsgc_tune& t) {
   const uint32_t small_log2 =
       uint32_t(std::max(ceil_log2(uint64_t(std::max(t.small_max, 1)) * 2), 6));
   L.lds_small = lds_small_bytes(small_log2);
-  L.lds_part = lds_part_bytes(L.max_buckets);
+  L.lds_part = lds_part_bytes(L.max_buckets, uint32_t(t.tile_log2));
   L.lds_link = lds_link_bytes(uint32_t(t.link_slots_log2), L.max_buckets);
   L.lds_rc = lds_rc_bytes(uint32_t(t.rc_slots_log2));
   return L;
@@ -186,19 +187,32 @@ int check_lds(const DevCtx* c, const Launch& L) {
   return m <= c->lds_limit ? NSGC_OK : NSGC_ERR_INVALID_ARG;
 }
 
-// Enqueue the kernels of one uploaded plan.  `fixed_grid` launches every
-// kernel with the full persistent grid (graph capture); otherwise grids are
-// trimmed to the item counts and empty phases are skipped.
+// Which kernels a plan needs: bit 0 the small-window kernel, bit 1 phases A-C.
+int plan_variant(const HostPlan& hp) {
+  return (hp.small.empty() ? 0 : 1) | (hp.win.empty() ? 0 : 2);
+}
+
+// Enqueue the kernels of one uploaded plan.  With `fixed_grid` (graph
+// capture) every kernel of `variant` is launched with the full persistent
+// grid; otherwise grids are trimmed to the item counts and empty phases are
+// skipped.
 int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch& L,
-                    uint32_t tile_log2, hipStream_t s, bool fixed_grid) {
+                    uint32_t tile_log2, hipStream_t s, bool fixed_grid, int variant,
+                    const hipEvent_t* ev = nullptr) {
   auto grid = [&](uint32_t items) { return fixed_grid ? L.grid_cap : std::min(items, L.grid_cap); };
-  if (fixed_grid || !hp.small.empty())
-    NSGC_HIP(launch_small(dplan, grid(uint32_t(hp.small.size())), L.lds_small, s));
-  if (fixed_grid || !hp.win.empty()) {
-    NSGC_HIP(launch_partition(dplan, tile_log2, grid(hp.itemsA), L.lds_part, s));
-    NSGC_HIP(launch_links(dplan, L.max_buckets, grid(hp.itemsB), L.lds_link, s));
-    NSGC_HIP(launch_rowcol(dplan, grid(hp.itemsC), L.lds_rc, s));
-  }
+  auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
+  const bool small = fixed_grid ? (variant & 1) != 0 : !hp.small.empty();
+  const bool part = fixed_grid ? (variant & 2) != 0 : !hp.win.empty();
+  NSGC_HIP(mark(0));
+  if (small) NSGC_HIP(launch_small(dplan, grid(uint32_t(hp.small.size())), L.lds_small, s));
+  NSGC_HIP(mark(1));
+  if (part)
+    NSGC_HIP(launch_partition(dplan, tile_log2, L.max_buckets, grid(hp.itemsA), L.lds_part, s));
+  NSGC_HIP(mark(2));
+  if (part) NSGC_HIP(launch_links(dplan, L.max_buckets, grid(hp.itemsB), L.lds_link, s));
+  NSGC_HIP(mark(3));
+  if (part) NSGC_HIP(launch_rowcol(dplan, grid(hp.itemsC), L.lds_rc, s));
+  NSGC_HIP(mark(4));
   return NSGC_OK;
 }
 
@@ -228,7 +242,7 @@ int get_slot(DevCtx* c, hipStream_t s, Slot** out) {
 
 // Upload one plan into slot `sl` and launch it.
 int run_plan(DevCtx* c, Slot* sl, const HostPlan& hp, const nsgc_tune& t, const uint32_t* src,
-             const uint32_t* dst, void* out, hipStream_t s) {
+             const uint32_t* dst, void* out, hipStream_t s, const hipEvent_t* ev = nullptr) {
   const Launch L = launch_params(c, t);
   int rc = check_lds(c, L);
   if (rc != NSGC_OK) return rc;
@@ -244,7 +258,7 @@ int run_plan(DevCtx* c, Slot* sl, const HostPlan& hp, const nsgc_tune& t, const 
   NSGC_HIP(hipEventRecord(sl->ev[k], s));
   sl->ev_used[k] = true;
   return enqueue_kernels(hp, reinterpret_cast<const nsgc_dev_plan*>(sl->plan_dev), L,
-                         hp.tile_log2, s, false);
+                         hp.tile_log2, s, false, 0, ev);
 }
 
 // Upper bound of the workspace for any batch within the limits.
@@ -307,6 +321,33 @@ int nsgc_window_stats(const uint32_t* src, const uint32_t* dst, const int64_t* w
   return run_plan(c, sl, hp, t, src, dst, out_stats, s);
 }
 
+int nsgc_window_stats_timed(const uint32_t* src, const uint32_t* dst,
+                            const int64_t* window_offsets, int64_t num_windows,
+                            nsgc_stats* out_stats, void* stream, float* phase_ms) {
+  if (!phase_ms) return NSGC_ERR_INVALID_ARG;
+  int rc = validate_common(src, dst, window_offsets, num_windows, out_stats);
+  if (rc != NSGC_OK) return rc;
+  for (int i = 0; i < 4; ++i) phase_ms[i] = 0.0f;
+  if (num_windows == 0) return NSGC_OK;
+  std::lock_guard<std::mutex> lock(g_mu);
+  const nsgc_tune t = current_tune();
+  HostPlan hp;
+  if ((rc = make_plan(window_offsets, num_windows, t, &hp)) != NSGC_OK) return rc;
+  DevCtx* c = nullptr;
+  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
+  Slot* sl = nullptr;
+  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
+  for (int i = 0; i < 5; ++i)
+    if (!sl->phase_ev[i]) NSGC_HIP(hipEventCreate(&sl->phase_ev[i]));
+  if ((rc = run_plan(c, sl, hp, t, src, dst, out_stats, s, sl->phase_ev)) != NSGC_OK) return rc;
+  NSGC_HIP(hipEventSynchronize(sl->phase_ev[4]));
+  for (int i = 0; i < 4; ++i)
+    NSGC_HIP(hipEventElapsedTime(&phase_ms[i], sl->phase_ev[i], sl->phase_ev[i + 1]));
+  return NSGC_OK;
+}
+
 int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
                             const int64_t* window_offsets, int64_t num_windows,
                             nsgc_stats* out_stats, void* stream) {
@@ -347,7 +388,7 @@ int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
   for (int64_t w = 0; w < num_windows; ++w) {
     rc = enqueue_kernels(plans[size_t(w)],
                          reinterpret_cast<const nsgc_dev_plan*>(sl->plan_dev + at[size_t(w)]), L,
-                         plans[size_t(w)].tile_log2, s, false);
+                         plans[size_t(w)].tile_log2, s, false, 0);
     if (rc != NSGC_OK) return rc;
   }
   return NSGC_OK;
@@ -390,6 +431,8 @@ int nsgc_release(void) {
       if (sl->stage[k]) (void)hipHostFree(sl->stage[k]);
       if (sl->ev[k]) (void)hipEventDestroy(sl->ev[k]);
     }
+    for (int k = 0; k < 5; ++k)
+      if (sl->phase_ev[k]) (void)hipEventDestroy(sl->phase_ev[k]);
     delete sl;
   }
   it->second->slots.clear();
@@ -468,8 +511,8 @@ struct nsgc_graph {
     char* plan_dev = nullptr;
     size_t plan_cap = 0;
     char* stage = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[4] = {};     // indexed by plan variant (see plan_variant)
+    hipGraphExec_t exec[4] = {};
     hipEvent_t done = nullptr;
     bool used = false;
   } inst[2];
@@ -480,7 +523,7 @@ struct nsgc_graph {
 
 namespace {
 
-int capture_instance(nsgc_graph* g, nsgc_graph::Inst& in) {
+int capture_instance(nsgc_graph* g, nsgc_graph::Inst& in, int variant) {
   NSGC_HIP(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipMemcpyAsync(in.plan_dev, in.stage, in.plan_cap, hipMemcpyHostToDevice,
                                 g->capture);
@@ -488,7 +531,7 @@ int capture_instance(nsgc_graph* g, nsgc_graph::Inst& in) {
   int rc = NSGC_OK;
   if (e == hipSuccess) {
     rc = enqueue_kernels(empty, reinterpret_cast<const nsgc_dev_plan*>(in.plan_dev), g->L,
-                         uint32_t(g->tune.tile_log2), g->capture, true);
+                         uint32_t(g->tune.tile_log2), g->capture, true, variant);
   }
   hipGraph_t graph = nullptr;
   const hipError_t e2 = hipStreamEndCapture(g->capture, &graph);
@@ -498,16 +541,18 @@ int capture_instance(nsgc_graph* g, nsgc_graph::Inst& in) {
     return rc;
   }
   if (e2 != hipSuccess) return hip_fail(e2);
-  in.graph = graph;
-  NSGC_HIP(hipGraphInstantiate(&in.exec, graph, nullptr, nullptr, 0));
+  in.graph[variant] = graph;
+  NSGC_HIP(hipGraphInstantiate(&in.exec[variant], graph, nullptr, nullptr, 0));
   return NSGC_OK;
 }
 
 void destroy_graph(nsgc_graph* g) {
   for (auto& in : g->inst) {
     if (in.done) (void)hipEventSynchronize(in.done);
-    if (in.exec) (void)hipGraphExecDestroy(in.exec);
-    if (in.graph) (void)hipGraphDestroy(in.graph);
+    for (int v = 0; v < 4; ++v) {
+      if (in.exec[v]) (void)hipGraphExecDestroy(in.exec[v]);
+      if (in.graph[v]) (void)hipGraphDestroy(in.graph[v]);
+    }
     if (in.plan_dev) (void)hipFree(in.plan_dev);
     if (in.stage) (void)hipHostFree(in.stage);
     if (in.done) (void)hipEventDestroy(in.done);
@@ -559,10 +604,6 @@ int nsgc_graph_create(int64_t max_packets, int64_t max_windows, nsgc_graph** out
       destroy_graph(g);
       return hip_fail(e);
     }
-    if ((rc = capture_instance(g, in)) != NSGC_OK) {
-      destroy_graph(g);
-      return rc;
-    }
   }
   if ((rc = ensure_device(&g->ws, &g->ws_cap, workspace_bound(max_packets, max_windows, g->tune),
                           g->capture)) != NSGC_OK) {
@@ -598,9 +639,11 @@ int nsgc_graph_launch(nsgc_graph* g, const uint32_t* src, const uint32_t* dst,
   }
   nsgc_graph::Inst& in = g->inst[g->next];
   if (in.used) NSGC_HIP(hipEventSynchronize(in.done));
+  const int variant = plan_variant(hp);
+  if (!in.exec[variant] && (rc = capture_instance(g, in, variant)) != NSGC_OK) return rc;
   hp.serialize(in.stage, reinterpret_cast<uint64_t>(in.plan_dev), reinterpret_cast<uint64_t>(g->ws),
                src, dst, out_stats);
-  NSGC_HIP(hipGraphLaunch(in.exec, s));
+  NSGC_HIP(hipGraphLaunch(in.exec[variant], s));
   NSGC_HIP(hipEventRecord(in.done, s));
   in.used = true;
   g->next ^= 1;

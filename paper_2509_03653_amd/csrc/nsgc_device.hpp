@@ -18,6 +18,33 @@ constexpr u64 EMPTY64 = ~0ull;
 constexpr uint32_t EMPTY32 = 0xFFFFFFFFu;
 constexpr int WAVES = NSGC_BLOCK / 64;
 
+// ---- global-memory pointers ------------------------------------------------
+// Pointers read out of the plan are generic to the compiler; generic (flat)
+// loads count against the LDS wait counter too, so an LDS wait would also
+// wait for every global load in flight.  Casting them to the global address
+// space keeps global loads and LDS operations on separate counters.
+#define NSGC_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ NSGC_GLOBAL T* gptr(T* p) {
+  return (NSGC_GLOBAL T*)(p);
+}
+
+// Load a descriptor struct (size a multiple of 8) from global memory.
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+  static_assert(sizeof(T) % 8 == 0, "descriptor size must be a multiple of 8");
+  const NSGC_GLOBAL u64* q = (const NSGC_GLOBAL u64*)(p);
+  u64 tmp[sizeof(T) / 8];
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 8; ++i) tmp[i] = q[i];
+  T out;
+  __builtin_memcpy(&out, tmp, sizeof(T));
+  return out;
+}
+
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+
 // ---- hashing: invertible xorshift / odd-multiply mixers ------------------
 // Bijections, so the bucket, sweep and slot bits taken from one mix of a key
 // can always be refined until a group holds a single key.
@@ -188,6 +215,61 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* pref, uint32_t coun
   return lo;
 }
 
+// Largest i in [0, count) with pref[i] <= x, for a non-decreasing array in
+// global memory with pref[0] <= x: a 64-ary search in which every lane of the
+// wavefront tests one probe per round (one memory round trip per 64x
+// narrowing).  Every wavefront computes the same result.
+__device__ __forceinline__ uint32_t owner_of_wave(const NSGC_GLOBAL uint32_t* pref, uint32_t count,
+                                                  uint32_t x) {
+  uint32_t lo = 0, n = count;
+  const uint32_t lane = lane_id();
+  while (n > 1) {
+    const uint32_t step = (n + 63) >> 6;
+    const uint32_t at = lane * step;
+    const bool ok = at < n && pref[lo + at] <= x;
+    const u64 m = __ballot(ok);
+    const uint32_t k = 63u - uint32_t(__clzll(static_cast<long long>(m)));
+    lo += k * step;
+    n = min(step, n - k * step);
+  }
+  return lo;
+}
+
+// Dynamic work queue: workgroups take items in order from an atomic counter,
+// so uneven items (heavy buckets, windows of very different sizes) spread over
+// the grid.  The next item is requested while the current one is processed.
+struct ItemQueue {
+  NSGC_GLOBAL uint32_t* counter;
+  uint32_t* slot;        // LDS word that broadcasts the item to the workgroup
+  uint32_t pending;      // thread 0: prefetched next item
+
+  __device__ __forceinline__ uint32_t take() {
+    return __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __device__ __forceinline__ uint32_t first(uint32_t items) {
+    if (threadIdx.x == 0) {
+      const uint32_t v = take();
+      slot[0] = v;
+      pending = v < items ? take() : items;
+    }
+    __syncthreads();
+    const uint32_t v = slot[0];
+    __syncthreads();
+    return v;
+  }
+  __device__ __forceinline__ uint32_t next(uint32_t items) {
+    if (threadIdx.x == 0) {
+      const uint32_t v = pending;
+      slot[0] = v;
+      pending = v < items ? take() : items;
+    }
+    __syncthreads();
+    const uint32_t v = slot[0];
+    __syncthreads();
+    return v;
+  }
+};
+
 // ---- LDS open-addressing tables (linear probing) --------------------------
 
 // Find or insert key (!= EMPTY64).  Returns the slot, or -1 when the table is
@@ -234,6 +316,110 @@ __device__ __forceinline__ int lds_insert32(uint32_t* tk, uint32_t mask, uint32_
   return -1;
 }
 
+// Compare-and-swap on LDS returning the previous value.
+__device__ __forceinline__ u64 lds_cas64(u64* p, u64 expect, u64 val) {
+  u64 e = expect;
+  __hip_atomic_compare_exchange_strong(p, &e, val, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+  return e;
+}
+__device__ __forceinline__ uint32_t lds_cas32(uint32_t* p, uint32_t expect, uint32_t val) {
+  uint32_t e = expect;
+  __hip_atomic_compare_exchange_strong(p, &e, val, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+  return e;
+}
+
+// Find-or-insert of U keys per thread in an open-addressing LDS table with
+// linear probing.  Stage 1 tries every key's home slot with one
+// compare-and-swap, all U issued together; at the low load factors used here
+// most keys settle there (the slot was empty, or already holds the key).
+// Stage 2 walks the remaining keys of each lane one probe at a time, so the
+// wavefront pays only for the probes that are actually left instead of
+// U-wide rounds.  Slots only go from empty to a key, so a key is never placed
+// twice.  slot[u] = the key's slot (-1 if not ok or out of probes), fresh[u]
+// = whether this call inserted it.  Returns false if a key ran out of probes.
+template <int U, class K>
+__device__ __forceinline__ bool cas_insert(K* tk, uint32_t mask, const K (&key)[U],
+                                           const uint32_t (&h)[U], const bool (&ok)[U],
+                                           int (&slot)[U], bool (&fresh)[U],
+                                           uint32_t max_probes) {
+  constexpr K EMPTY = K(~K(0));
+  K old[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    slot[u] = -1;
+    fresh[u] = false;
+    old[u] = EMPTY;
+    if (ok[u]) {
+      K* at = tk + (h[u] & mask);
+      if constexpr (sizeof(K) == 8)
+        old[u] = lds_cas64(reinterpret_cast<u64*>(at), EMPTY64, key[u]);
+      else
+        old[u] = lds_cas32(reinterpret_cast<uint32_t*>(at), EMPTY32, key[u]);
+    }
+  }
+  uint32_t pending = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (ok[u]) {
+      if (old[u] == EMPTY || old[u] == key[u]) {
+        slot[u] = int(h[u] & mask);
+        fresh[u] = old[u] == EMPTY;
+      } else {
+        pending |= 1u << u;
+      }
+    }
+  }
+  bool gave_up = false;
+  while (pending) {
+    const int cu = __builtin_ctz(pending);
+    K ck = 0;
+    uint32_t cp = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (u == cu) { ck = key[u]; cp = h[u]; }
+    int got = -1;
+    bool fr = false;
+    for (uint32_t probe = 1; probe < max_probes; ++probe) {
+      const uint32_t s = (cp + probe) & mask;
+      K o;
+      if constexpr (sizeof(K) == 8)
+        o = lds_cas64(reinterpret_cast<u64*>(tk + s), EMPTY64, ck);
+      else
+        o = lds_cas32(reinterpret_cast<uint32_t*>(tk + s), EMPTY32, ck);
+      if (o == EMPTY || o == ck) {
+        got = int(s);
+        fr = o == EMPTY;
+        break;
+      }
+    }
+    if (got < 0) gave_up = true;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (u == cu) { slot[u] = got; fresh[u] = fr; }
+    pending &= pending - 1;
+  }
+  return !gave_up;
+}
+
+// Largest i < cn with off[i] <= j[u] for U queries at once (off non-decreasing,
+// off[0] = 0): a branch-free binary search whose LDS reads for the U queries
+// are issued together each round.
+template <int U>
+__device__ __forceinline__ void lockstep_owner(const uint32_t* off, uint32_t cn,
+                                               const uint32_t (&j)[U], uint32_t (&idx)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) idx[u] = 0;
+  for (uint32_t s = cn > 1 ? (1u << (31 - __clz(cn - 1))) : 0u; s; s >>= 1) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t c = idx[u] + s;
+      if (c < cn && off[c] <= j[u]) idx[u] = c;
+    }
+  }
+}
+
 __device__ __forceinline__ uint32_t lds_add(uint32_t* p, uint32_t v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -248,11 +434,11 @@ __device__ __forceinline__ void lds_store(uint32_t* p, uint32_t v) {
 
 // ---- global combine of partial statistics ---------------------------------
 
-__device__ __forceinline__ void stat_add(u64* out, u64 v) {
-  if (v) atomicAdd(out, v);
+__device__ __forceinline__ void stat_add(NSGC_GLOBAL u64* out, u64 v) {
+  if (v) __hip_atomic_fetch_add(out, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void stat_max(u64* out, u64 v) {
-  if (v) atomicMax(out, v);
+__device__ __forceinline__ void stat_max(NSGC_GLOBAL u64* out, u64 v) {
+  if (v) __hip_atomic_fetch_max(out, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace nsgc

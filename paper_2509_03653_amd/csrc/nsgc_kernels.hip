@@ -4,11 +4,17 @@
 // its src/dst reverse).  Packets are packed into 64-bit keys src << 32 | dst;
 // A(s,d) is the multiplicity of a key.  No contraction is involved, so no
 // matrix cores are used: the work is hashing, LDS aggregation and
-// order-independent integer reductions.
+// order-independent integer reductions, bound by memory and LDS latency.
 //
-// Every kernel is persistent: a fixed grid of workgroups strides over the work
-// items whose count is read from the device plan, so a captured graph can
-// replay any batch that fits its workspace.
+// Latency is the enemy here, so every per-element loop works on NSGC_UNROLL
+// elements per thread in lockstep: segment searches, global loads and LDS
+// compare-and-swap probes of the U elements are issued together and their
+// round trips overlap.
+//
+// The kernels that take uneven items (small windows, phases B and C) draw them
+// from an atomic work queue; the partition kernel strides over its uniform
+// tiles.  Grids are persistent, so a captured graph replays any batch that
+// fits its workspace.
 #include <hip/hip_runtime.h>
 
 #include "nsgc_device.hpp"
@@ -20,15 +26,20 @@ namespace {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
+constexpr int U = NSGC_UNROLL;
+// Probes before an insert of phases B and C gives up; the caller then splits
+// the keys into sweeps, so giving up never changes a result.
+constexpr uint32_t NSGC_MAX_PROBES = 64;
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Tier "small": one workgroup per window, everything in LDS.
 //
 // Per packet: find-or-insert the link key (the inserting lane learns that the
-// link is new), add one packet to the link; add one packet to the source's row
+// link is new) and add one packet to it; add one packet to the source's row
 // and, if the link is new, one link to its fan-out; the same for the
-// destination's column.  Tables hold 2^k >= 2 n slots, so they never fill.
+// destination's column.  Tables hold 2^k >= 2 n slots.
 // ---------------------------------------------------------------------------
 
 size_t lds_small_bytes(uint32_t slots_log2) {
@@ -36,10 +47,9 @@ size_t lds_small_bytes(uint32_t slots_log2) {
   return align16(S * 8) + align16(S * 4) * 7 + 256;
 }
 
-__global__ __launch_bounds__(NSGC_BLOCK) void k_small(const nsgc_dev_plan* __restrict__ P) {
+__global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t S = 1u << P->small_slots_log2;
-  const uint32_t mask = S - 1;
   u64* lk = reinterpret_cast<u64*>(smem);
   uint32_t* lc = reinterpret_cast<uint32_t*>(smem + align16(S * 8));
   uint32_t* rk = lc + S;
@@ -49,12 +59,14 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(const nsgc_dev_plan* __res
   uint32_t* cp = ck + S;
   uint32_t* cf = cp + S;
   uint32_t* misc = cf + S;  // [0] special link count, [1] special link seen,
-                            // [2,3] special row (packets, links), [4,5] special column
+                            // [2,3] special row (packets, links), [4,5] special
+                            // column, [6] failure flag, [7] queue slot
   uint32_t* red = misc + 8;
 
   const uint32_t items = P->num_small;
-  for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const nsgc_small_desc D = P->small[item];
+  ItemQueue q{gptr(&P->queue[0]), misc + 7, 0};
+  for (uint32_t item = q.first(items); item < items; item = q.next(items)) {
+    const nsgc_small_desc D = gload(P->small + item);
     for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
       lk[i] = EMPTY64;
       lc[i] = 0;
@@ -65,40 +77,74 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(const nsgc_dev_plan* __res
       cp[i] = 0;
       cf[i] = 0;
     }
-    if (threadIdx.x < 8) misc[threadIdx.x] = 0;
+    if (threadIdx.x < 7) misc[threadIdx.x] = 0;
     __syncthreads();
 
-    const uint32_t* src = P->src + D.in_begin;
-    const uint32_t* dst = P->dst + D.in_begin;
-    for (uint32_t j = threadIdx.x; j < D.n; j += NSGC_BLOCK) {
-      const uint32_t s = src[j];
-      const uint32_t d = dst[j];
-      const u64 key = (u64(s) << 32) | d;
-      bool fresh;
-      if (key == EMPTY64) {
-        fresh = lds_add(&misc[1], 1) == 0;
-        lds_add(&misc[0], 1);
-      } else {
-        const int slot = lds_insert64(lk, mask, key, uint32_t(link_hash(key)), fresh);
-        lds_add(&lc[slot], 1);
+    const NSGC_GLOBAL uint32_t* src = gptr(P->src) + D.in_begin;
+    const NSGC_GLOBAL uint32_t* dst = gptr(P->dst) + D.in_begin;
+    for (uint32_t j0 = 0; j0 < D.n; j0 += U * NSGC_BLOCK) {
+      uint32_t s[U], d[U], h[U];
+      u64 key[U];
+      bool ok[U], fresh[U], tab[U], rt[U];
+      int slot[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t j = j0 + u * NSGC_BLOCK + threadIdx.x;
+        ok[u] = j < D.n;
+        s[u] = ok[u] ? src[j] : 0u;
+        d[u] = ok[u] ? dst[j] : 0u;
       }
-      if (s == EMPTY32) {
-        lds_add(&misc[2], 1);
-        if (fresh) lds_add(&misc[3], 1);
-      } else {
-        bool f2;
-        const int slot = lds_insert32(rk, mask, s, row_hash(s), f2);
-        lds_add(&rp[slot], 1);
-        if (fresh) lds_add(&rf[slot], 1);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        key[u] = (u64(s[u]) << 32) | d[u];
+        h[u] = uint32_t(link_hash(key[u]));
+        // the key equal to the empty marker is counted outside the table
+        tab[u] = ok[u] && key[u] != EMPTY64;
       }
-      if (d == EMPTY32) {
-        lds_add(&misc[4], 1);
-        if (fresh) lds_add(&misc[5], 1);
-      } else {
-        bool f2;
-        const int slot = lds_insert32(ck, mask, d, col_hash(d), f2);
-        lds_add(&cp[slot], 1);
-        if (fresh) lds_add(&cf[slot], 1);
+      if (!cas_insert<U>(lk, S - 1, key, h, tab, slot, fresh, S + 1)) lds_store(&misc[6], 1);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ok[u] && !tab[u]) {
+          fresh[u] = lds_add(&misc[1], 1) == 0;
+          lds_add(&misc[0], 1);
+        }
+        if (slot[u] >= 0) lds_add(&lc[slot[u]], 1);
+      }
+      // rows
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        rt[u] = ok[u] && s[u] != EMPTY32;
+        h[u] = row_hash(s[u]);
+      }
+      if (!cas_insert<U>(rk, S - 1, s, h, rt, slot, tab, S + 1)) lds_store(&misc[6], 1);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ok[u] && !rt[u]) {
+          lds_add(&misc[2], 1);
+          if (fresh[u]) lds_add(&misc[3], 1);
+        }
+        if (slot[u] >= 0) {
+          lds_add(&rp[slot[u]], 1);
+          if (fresh[u]) lds_add(&rf[slot[u]], 1);
+        }
+      }
+      // columns
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        rt[u] = ok[u] && d[u] != EMPTY32;
+        h[u] = col_hash(d[u]);
+      }
+      if (!cas_insert<U>(ck, S - 1, d, h, rt, slot, tab, S + 1)) lds_store(&misc[6], 1);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ok[u] && !rt[u]) {
+          lds_add(&misc[4], 1);
+          if (fresh[u]) lds_add(&misc[5], 1);
+        }
+        if (slot[u] >= 0) {
+          lds_add(&cp[slot[u]], 1);
+          if (fresh[u]) lds_add(&cf[slot[u]], 1);
+        }
       }
     }
     __syncthreads();
@@ -121,10 +167,13 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(const nsgc_dev_plan* __res
     uint32_t zero = 0;
     block_sum_max(zero, mg, red);
     if (threadIdx.x == 0) {
-      u64* o = P->out + u64(D.out_index) * 9;
-      o[0] = sl; o[1] = nl; o[2] = ml;
-      o[3] = nr; o[4] = mr; o[5] = mf;
-      o[6] = nc; o[7] = mc; o[8] = mg;
+      // tables of >= 2n slots cannot fill; a failure would be a library bug,
+      // reported as all-ones statistics rather than silently wrong numbers
+      const bool bad = misc[6] != 0;
+      NSGC_GLOBAL u64* o = gptr(P->out) + u64(D.out_index) * 9;
+      o[0] = bad ? ~0ull : sl; o[1] = bad ? ~0ull : nl; o[2] = bad ? ~0ull : ml;
+      o[3] = bad ? ~0ull : nr; o[4] = bad ? ~0ull : mr; o[5] = bad ? ~0ull : mf;
+      o[6] = bad ? ~0ull : nc; o[7] = bad ? ~0ull : mc; o[8] = bad ? ~0ull : mg;
     }
     __syncthreads();
   }
@@ -132,74 +181,94 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(const nsgc_dev_plan* __res
 
 // ---------------------------------------------------------------------------
 // Phase A: partition a tile of packets by link bucket.
-// Each thread holds PER packets in registers; an LDS histogram gives every
-// packet its rank inside its bucket, a block scan gives the bucket starts, and
-// the keys are written to the tile's region in bucket order.
+//
+// Each thread holds PER packets in registers (16-byte loads when the tile is
+// aligned).  An LDS histogram gives every packet its rank in its bucket, a
+// block scan gives the bucket starts, the keys are placed in LDS in bucket
+// order and leave in full coalesced lines.  The tile's bucket starts go to
+// the bucket-major tile table.
 // ---------------------------------------------------------------------------
 
-size_t lds_part_bytes(uint32_t max_buckets) { return align16((max_buckets + 1) * 4) + 256; }
+size_t lds_part_bytes(uint32_t max_buckets, uint32_t tile_log2) {
+  return align16((max_buckets + 1) * 4) + align16((size_t(1) << tile_log2) * 8) + 256;
+}
 
 template <int PER>
-__global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* __restrict__ P) {
+__global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* __restrict__ P,
+                                                          uint32_t max_buckets) {
+  static_assert(PER % 4 == 0, "PER must be a multiple of 4");
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr uint32_t T = NSGC_BLOCK * PER;
   uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
+  u64* stage = reinterpret_cast<u64*>(smem + align16((max_buckets + 1) * 4));
+  uint32_t* red = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(stage) + T * 8);
   const uint32_t items = P->itemsA;
-  const uint32_t T = NSGC_BLOCK * PER;
-  uint32_t* red = nullptr;
   for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const uint32_t wi = owner_of(P->prefA, P->num_part, item);
-    const nsgc_win_desc W = P->win[wi];
-    const uint32_t t = item - P->prefA[wi];
+    const uint32_t wi = owner_of_wave(gptr(P->prefA), P->num_part, item);
+    const nsgc_win_desc W = gload(P->win + wi);
+    const uint32_t t = item - gptr(P->prefA)[wi];
     const uint32_t B = 1u << W.logB;
-    red = hist + ((B + 1 + 3) & ~3u);
     const uint32_t tbeg = t * T;
     const uint32_t len = min(T, W.n - tbeg);
     for (uint32_t i = threadIdx.x; i < B; i += NSGC_BLOCK) hist[i] = 0;
-    if (t == 0) {
-      if (threadIdx.x < 9) P->out[u64(W.out_index) * 9 + threadIdx.x] = 0;
-      if (threadIdx.x == 0) P->counters[W.counter] = 0;
-    }
+    if (t == 0 && threadIdx.x < 9) gptr(P->out)[u64(W.out_index) * 9 + threadIdx.x] = 0;
     __syncthreads();
 
-    const uint32_t* src = P->src + W.in_begin + tbeg;
-    const uint32_t* dst = P->dst + W.in_begin + tbeg;
+    const uint64_t gbeg = uint64_t(W.in_begin) + tbeg;
+    const NSGC_GLOBAL uint32_t* src = gptr(P->src) + gbeg;
+    const NSGC_GLOBAL uint32_t* dst = gptr(P->dst) + gbeg;
     u64 key[PER];
     uint32_t bk[PER], rk[PER];
+    bool ok[PER];
+    const bool aligned = ((reinterpret_cast<uintptr_t>(P->src + gbeg) |
+                           reinterpret_cast<uintptr_t>(P->dst + gbeg)) & 15) == 0;
+    if (aligned && len == T) {
+      // full aligned tile: each thread loads 4 consecutive packets per step
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const uint32_t idx = k * NSGC_BLOCK + threadIdx.x;
-      if (idx < len) {
-        key[k] = (u64(src[idx]) << 32) | dst[idx];
+      for (int k = 0; k < PER / 4; ++k) {
+        const uint32_t idx = (k * NSGC_BLOCK + threadIdx.x) * 4;
+        const v4u32 s4 = *(const NSGC_GLOBAL v4u32*)(src + idx);
+        const v4u32 d4 = *(const NSGC_GLOBAL v4u32*)(dst + idx);
+        key[4 * k + 0] = (u64(s4.x) << 32) | d4.x;
+        key[4 * k + 1] = (u64(s4.y) << 32) | d4.y;
+        key[4 * k + 2] = (u64(s4.z) << 32) | d4.z;
+        key[4 * k + 3] = (u64(s4.w) << 32) | d4.w;
+        ok[4 * k + 0] = ok[4 * k + 1] = ok[4 * k + 2] = ok[4 * k + 3] = true;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const uint32_t idx = k * NSGC_BLOCK + threadIdx.x;
+        ok[k] = idx < len;
+        key[k] = ok[k] ? ((u64(src[idx]) << 32) | dst[idx]) : 0ull;
       }
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const uint32_t idx = k * NSGC_BLOCK + threadIdx.x;
-      if (idx < len) {
+      if (ok[k]) {
         bk[k] = top64(link_hash(key[k]), W.logB);
         rk[k] = lds_add(&hist[bk[k]], 1);
       }
     }
     __syncthreads();
     block_exclusive_scan(hist, B, red);
-    uint32_t* tm = P->tilemeta + W.tilemeta + u64(t) * (B + 1);
-    for (uint32_t i = threadIdx.x; i <= B; i += NSGC_BLOCK) tm[i] = hist[i];
-    u64* out = P->keys + W.ws + tbeg;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const uint32_t idx = k * NSGC_BLOCK + threadIdx.x;
-      if (idx < len) out[hist[bk[k]] + rk[k]] = key[k];
-    }
+    for (int k = 0; k < PER; ++k)
+      if (ok[k]) stage[hist[bk[k]] + rk[k]] = key[k];
+    NSGC_GLOBAL uint32_t* tm = gptr(P->tilemeta) + W.tilemeta + t;
+    for (uint32_t i = threadIdx.x; i <= B; i += NSGC_BLOCK) tm[u64(i) * W.ntiles] = hist[i];
+    __syncthreads();
+    NSGC_GLOBAL u64* out = gptr(P->keys) + W.ws + tbeg;
+    for (uint32_t i = threadIdx.x; i < len; i += NSGC_BLOCK) out[i] = stage[i];
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Shared machinery of phases B and C: stream the elements of up to
-// NSGC_MAX_SEG segments at a time.  Segment i holds `seg_len` elements
-// starting at element `seg_base` of some array; the callback gets the flat
-// element position (and a validity flag) with the whole wavefront active,
-// so it may use wavefront-wide operations.
+// Shared machinery of phases B and C: visit the elements of up to
+// NSGC_MAX_SEG segments at a time, U per thread per round.  `seg(i, base,
+// len)` describes segment i; `fn(pos, ok)` receives the U flat positions
+// (pos[u] valid when ok[u]) with the whole wavefront active.
 // ---------------------------------------------------------------------------
 
 struct SegStage {
@@ -208,9 +277,9 @@ struct SegStage {
   uint32_t* red;   // [2 * WAVES]
 };
 
-template <class SegFn, class ElemFn>
-__device__ __forceinline__ void for_each_segment_element(uint32_t nseg, const SegStage& st,
-                                                         SegFn seg, ElemFn fn) {
+template <class SegFn, class BatchFn>
+__device__ __forceinline__ void gather_segments(uint32_t nseg, const SegStage& st, SegFn seg,
+                                                BatchFn fn) {
   for (uint32_t c0 = 0; c0 < nseg; c0 += NSGC_MAX_SEG) {
     const uint32_t cn = min(uint32_t(NSGC_MAX_SEG), nseg - c0);
     for (uint32_t i = threadIdx.x; i < cn; i += NSGC_BLOCK) {
@@ -222,15 +291,20 @@ __device__ __forceinline__ void for_each_segment_element(uint32_t nseg, const Se
     }
     __syncthreads();
     const uint32_t total = block_exclusive_scan(st.off, cn, st.red);
-    for (uint32_t j0 = 0; j0 < total; j0 += NSGC_BLOCK) {
-      const uint32_t j = j0 + threadIdx.x;
-      const bool valid = j < total;
-      u64 pos = 0;
-      if (valid) {
-        const uint32_t i = owner_of(st.off, cn, j);
-        pos = st.base[i] + (j - st.off[i]);
+    for (uint32_t j0 = 0; j0 < total; j0 += U * NSGC_BLOCK) {
+      uint32_t j[U], idx[U];
+      bool ok[U];
+      u64 pos[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        j[u] = j0 + u * NSGC_BLOCK + threadIdx.x;
+        ok[u] = j[u] < total;
+        if (!ok[u]) j[u] = 0;
       }
-      fn(pos, valid);
+      lockstep_owner<U>(st.off, cn, j, idx);
+#pragma unroll
+      for (int u = 0; u < U; ++u) pos[u] = st.base[idx[u]] + (j[u] - st.off[idx[u]]);
+      fn(pos, ok);
     }
     __syncthreads();
   }
@@ -240,324 +314,419 @@ __device__ __forceinline__ void for_each_segment_element(uint32_t nseg, const Se
 // Phase B: link aggregation of one link bucket.
 //
 // The bucket's keys are gathered from every tile of the window into an LDS
-// table key -> packet count (duplicates of the first active lane's key are
+// table key -> packet count (duplicates of the first valid lane's key are
 // combined with one ballot first, which keeps heavy links from serialising on
-// one LDS address).  If the bucket holds more distinct keys than the table's
-// load limit, it is split into 2^s sweeps by further hash bits and redone;
-// the split is a partition of the keys, so the result is unchanged.  The
-// table gives the bucket's share of stats 0-2; its links are then emitted as
-// (src, count) grouped by row bucket and (dst, count) grouped by column
-// bucket.
+// one LDS address).  Every newly inserted slot is also appended to a list of
+// occupied slots, so everything after the inserts (statistics, emission and
+// resetting the table for the next item) costs per link, not per slot.  The
+// table gives the bucket's share of stats 0-2; its links are emitted as
+// (src, packets) grouped by row bucket and (dst, packets) grouped by column
+// bucket into the bucket's emission region.
+//
+// If an insert gives up (more distinct keys than the table holds), the bucket
+// is split into 2^s sweeps by further hash bits and redone; the sweeps
+// partition the keys, so the result is unchanged.  With sweeps, every sweep
+// emits its own links, counted in a first pass and written in a second.
 // ---------------------------------------------------------------------------
 
 size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_buckets) {
   const size_t S = size_t(1) << slots_log2;
-  return align16(S * 8) + align16(S * 4) + align16(NSGC_MAX_SEG * 8) +
+  return align16(S * 8) + align16(S * 4) + align16(S * 4) + align16(NSGC_MAX_SEG * 8) +
          align16((NSGC_MAX_SEG + 1) * 4) + 2 * align16((max_buckets + 1) * 4) + 256;
 }
 
-__global__ __launch_bounds__(NSGC_BLOCK) void k_links(const nsgc_dev_plan* __restrict__ P,
-                                                      uint32_t max_buckets) {
+__global__ __launch_bounds__(NSGC_BLOCK) void k_links(nsgc_dev_plan* P, uint32_t max_buckets) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t S = 1u << P->link_slots_log2;
-  const uint32_t mask = S - 1;
-  const uint32_t limit = S - (S >> 2);
   unsigned char* p = smem;
   u64* tk = reinterpret_cast<u64*>(p);                 p += align16(S * 8);
   uint32_t* tc = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
+  uint32_t* occ = reinterpret_cast<uint32_t*>(p);      p += align16(S * 4);
   SegStage st;
   st.base = reinterpret_cast<u64*>(p);                 p += align16(NSGC_MAX_SEG * 8);
   st.off = reinterpret_cast<uint32_t*>(p);             p += align16((NSGC_MAX_SEG + 1) * 4);
   uint32_t* histR = reinterpret_cast<uint32_t*>(p);    p += align16((max_buckets + 1) * 4);
   uint32_t* histC = reinterpret_cast<uint32_t*>(p);    p += align16((max_buckets + 1) * 4);
-  uint32_t* misc = reinterpret_cast<uint32_t*>(p);     // [0] occupancy [1] overflow
-                                                       // [2] special count [3] emission base
+  uint32_t* misc = reinterpret_cast<uint32_t*>(p);
+  // misc: [0] fail flag, [1] special link count, [4] emission base,
+  // [5] occupied slots, [7] queue slot, [8..24) reduction scratch
   st.red = misc + 8;
+
+  // the table starts empty; every item leaves it empty again
+  for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
+    tk[i] = EMPTY64;
+    tc[i] = 0;
+  }
+  if (threadIdx.x == 0) misc[5] = 0;
 
   const uint32_t T = 1u << P->tile_log2;
   const uint32_t items = P->itemsB;
-  for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const uint32_t wi = owner_of(P->prefB, P->num_part, item);
-    const nsgc_win_desc W = P->win[wi];
-    const uint32_t b = item - P->prefB[wi];
+  ItemQueue q{gptr(&P->queue[1]), misc + 7, 0};
+  for (uint32_t item = q.first(items); item < items; item = q.next(items)) {
+    const uint32_t wi = owner_of_wave(gptr(P->prefB), P->num_part, item);
+    const nsgc_win_desc W = gload(P->win + wi);
+    const uint32_t b = item - gptr(P->prefB)[wi];
     const uint32_t B = 1u << W.logB, R = 1u << W.logR, C = 1u << W.logC;
-    const u64* keys = P->keys + W.ws;
-    const uint32_t* tm = P->tilemeta + W.tilemeta;
+    const uint32_t nt = W.ntiles;
+    const NSGC_GLOBAL u64* keys = gptr(P->keys) + W.ws;
+    const NSGC_GLOBAL uint32_t* tm0 = gptr(P->tilemeta) + W.tilemeta + u64(b) * nt;  // bucket b
+    const NSGC_GLOBAL uint32_t* tm1 = tm0 + nt;                                      // bucket b+1
+    NSGC_GLOBAL uint32_t* rec = gptr(P->lbmeta) + W.lbmeta;
 
-    auto seg = [&](uint32_t t, u64& base, uint32_t& len) {
-      const uint32_t* row = tm + u64(t) * (B + 1);
-      const uint32_t s0 = row[b], s1 = row[b + 1];
-      base = u64(t) * T + s0;
+    if (threadIdx.x == 0) misc[4] = 0;
+    __syncthreads();
+    {  // emission base: packets of the window in link buckets below b
+      uint32_t below = 0;
+      for (uint32_t t = threadIdx.x; t < nt; t += NSGC_BLOCK) below += tm0[t];
+      below = wave_sum(below);
+      if (lane_id() == 0 && below) lds_add(&misc[4], below);
+    }
+
+    auto seg = [&](uint32_t t, u64& sbase, uint32_t& len) {
+      const uint32_t s0 = tm0[t], s1 = tm1[t];
+      sbase = u64(t) * T + s0;
       len = s1 - s0;
     };
 
-    // Build the table for sweep `sw` of 2^logS.
-    auto build = [&](uint32_t logS, uint32_t sw) {
-      for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
-        tk[i] = EMPTY64;
-        tc[i] = 0;
+    // Empty the table through the occupied-slot list.
+    auto reset = [&]() {
+      const uint32_t n = misc[5];
+      for (uint32_t i = threadIdx.x; i < n; i += NSGC_BLOCK) {
+        const uint32_t s = occ[i];
+        tk[s] = EMPTY64;
+        tc[s] = 0;
       }
-      if (threadIdx.x < 4) misc[threadIdx.x] = 0;
       __syncthreads();
-      for_each_segment_element(W.ntiles, st, seg, [&](u64 pos, bool valid) {
-        u64 key = 0;
-        u64 h = 0;
-        if (valid) {
-          key = keys[pos];
-          h = link_hash(key);
-          if (logS && next64(h, W.logB, logS) != sw) valid = false;
-        }
-        if (valid && key == EMPTY64) {
-          lds_add(&misc[2], 1);
-          valid = false;
-        }
-        if (valid && lds_load(&misc[1])) valid = false;
-        const u64 vm = __ballot(valid);
-        if (!vm) return;
-        const int first = __ffsll(static_cast<unsigned long long>(vm)) - 1;
-        const u64 k0 = (u64(readlane(uint32_t(key >> 32), first)) << 32) |
-                       readlane(uint32_t(key), first);
-        const bool same = valid && key == k0;
-        const u64 sm = __ballot(same);
-        const uint32_t nsame = __popcll(sm);
-        uint32_t add = 1;
-        if (same) {
-          if (int(lane_id()) != first) valid = false;
-          else add = nsame;
-        }
-        if (valid) {
-          bool fresh;
-          const int slot = lds_insert64(tk, mask, key, uint32_t(h), fresh);
-          if (slot < 0) {
-            lds_store(&misc[1], 1);
-          } else {
-            if (fresh && lds_add(&misc[0], 1) >= limit) lds_store(&misc[1], 1);
-            lds_add(&tc[slot], add);
+      if (threadIdx.x == 0) misc[5] = 0;
+      __syncthreads();
+    };
+
+    // Link table of sweep `sw` of 2^logS.
+    auto build = [&](uint32_t logS, uint32_t sw) {
+      if (threadIdx.x < 2) misc[threadIdx.x] = 0;
+      __syncthreads();
+      gather_segments(nt, st, seg, [&](const u64 (&pos)[U], const bool (&okin)[U]) {
+        u64 key[U];
+        uint32_t h[U], add[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) key[u] = okin[u] ? keys[pos[u]] : 0ull;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const u64 hh = link_hash(key[u]);
+          h[u] = uint32_t(hh);
+          ok[u] = okin[u] && !(logS && next64(hh, W.logB, logS) != sw);
+          add[u] = 1;
+          if (ok[u] && key[u] == EMPTY64) {
+            lds_add(&misc[1], 1);
+            ok[u] = false;
           }
+          // combine the lanes holding the first valid lane's key
+          const u64 vm = __ballot(ok[u]);
+          if (vm) {
+            const int first = __ffsll(static_cast<unsigned long long>(vm)) - 1;
+            const u64 k0 = (u64(readlane(uint32_t(key[u] >> 32), first)) << 32) |
+                           readlane(uint32_t(key[u]), first);
+            const bool same = ok[u] && key[u] == k0;
+            const uint32_t nsame = __popcll(__ballot(same));
+            if (nsame > 1 && same) {
+              if (int(lane_id()) == first) add[u] = nsame;
+              else ok[u] = false;
+            }
+          }
+        }
+        int slot[U];
+        bool fresh[U];
+        if (!cas_insert<U>(tk, S - 1, key, h, ok, slot, fresh, NSGC_MAX_PROBES))
+          lds_store(&misc[0], 1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (slot[u] >= 0) lds_add(&tc[slot[u]], add[u]);
+          if (fresh[u]) occ[lds_add(&misc[5], 1)] = uint32_t(slot[u]);
         }
       });
     };
 
-    uint32_t logS = 0;
+    // Count (or, with cursors, write) the links per row and column bucket.
+    auto count = [&]() {
+      const uint32_t n = misc[5];
+      for (uint32_t i = threadIdx.x; i < n; i += NSGC_BLOCK) {
+        const u64 key = tk[occ[i]];
+        lds_add(&histR[top32(row_hash(uint32_t(key >> 32)), W.logR)], 1);
+        lds_add(&histC[top32(col_hash(uint32_t(key)), W.logC)], 1);
+      }
+      if (threadIdx.x == 0 && misc[1]) {
+        lds_add(&histR[top32(row_hash(EMPTY32), W.logR)], 1);
+        lds_add(&histC[top32(col_hash(EMPTY32), W.logC)], 1);
+      }
+    };
+    auto emit = [&]() {
+      const uint32_t base = misc[4];
+      NSGC_GLOBAL u64* er = gptr(P->emit_row) + W.ws + base;
+      NSGC_GLOBAL u64* ec = gptr(P->emit_col) + W.ws + base;
+      const uint32_t n = misc[5];
+      for (uint32_t i0 = 0; i0 < n; i0 += U * NSGC_BLOCK) {
+        u64 key[U];
+        uint32_t cnt[U], ar[U], ac[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t i = i0 + u * NSGC_BLOCK + threadIdx.x;
+          ok[u] = i < n;
+          const uint32_t s = ok[u] ? occ[i] : 0u;
+          key[u] = ok[u] ? tk[s] : 0ull;
+          cnt[u] = ok[u] ? tc[s] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (ok[u]) {
+            ar[u] = lds_add(&histR[top32(row_hash(uint32_t(key[u] >> 32)), W.logR)], 1);
+            ac[u] = lds_add(&histC[top32(col_hash(uint32_t(key[u])), W.logC)], 1);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (ok[u]) {
+            er[ar[u]] = (key[u] & 0xFFFFFFFF00000000ull) | cnt[u];
+            ec[ac[u]] = (key[u] << 32) | cnt[u];
+          }
+        }
+      }
+      if (threadIdx.x == 0 && misc[1]) {
+        const uint32_t c = misc[1];
+        er[lds_add(&histR[top32(row_hash(EMPTY32), W.logR)], 1)] = (u64(EMPTY32) << 32) | c;
+        ec[lds_add(&histC[top32(col_hash(EMPTY32), W.logC)], 1)] = (u64(EMPTY32) << 32) | c;
+      }
+      __syncthreads();
+    };
+    auto publish = [&]() {
+      block_exclusive_scan(histR, R, st.red);
+      block_exclusive_scan(histC, C, st.red);
+      for (uint32_t i = threadIdx.x; i <= R; i += NSGC_BLOCK) rec[B + u64(i) * B + b] = histR[i];
+      for (uint32_t i = threadIdx.x; i <= C; i += NSGC_BLOCK)
+        rec[B + u64(R + 1) * B + u64(i) * B + b] = histC[i];
+    };
+
+    // Attempt with 2^logS sweeps; any insert that gives up restarts the whole
+    // bucket with twice the sweeps (the emission is rewritten from scratch).
     uint32_t links = 0, sum = 0, mx = 0;
-    for (;;) {
+    for (uint32_t logS = 0;; ++logS) {
       links = sum = mx = 0;
       for (uint32_t i = threadIdx.x; i < R; i += NSGC_BLOCK) histR[i] = 0;
       for (uint32_t i = threadIdx.x; i < C; i += NSGC_BLOCK) histC[i] = 0;
       bool failed = false;
+      // pass 1: statistics and link counts (one sweep also emits directly)
       for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
         build(logS, sw);
-        if (misc[1]) { failed = true; break; }
-        for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
-          const u64 key = tk[i];
-          if (key != EMPTY64) {
-            const uint32_t c = tc[i];
-            ++links;
-            sum += c;
-            mx = max(mx, c);
-            lds_add(&histR[top32(row_hash(uint32_t(key >> 32)), W.logR)], 1);
-            lds_add(&histC[top32(col_hash(uint32_t(key)), W.logC)], 1);
-          }
-        }
-        if (threadIdx.x == 0 && misc[2]) {
-          const uint32_t c = misc[2];
-          ++links;
+        if (misc[0]) { failed = true; reset(); break; }
+        const uint32_t n = misc[5];
+        for (uint32_t i = threadIdx.x; i < n; i += NSGC_BLOCK) {
+          const uint32_t c = tc[occ[i]];
           sum += c;
           mx = max(mx, c);
-          lds_add(&histR[top32(row_hash(EMPTY32), W.logR)], 1);
-          lds_add(&histC[top32(col_hash(EMPTY32), W.logC)], 1);
         }
+        if (threadIdx.x == 0) {
+          links += n;
+          if (misc[1]) {
+            ++links;
+            sum += misc[1];
+            mx = max(mx, misc[1]);
+          }
+        }
+        count();
         __syncthreads();
+        if (logS == 0) {
+          publish();
+          __syncthreads();
+          emit();
+        }
+        reset();
+      }
+      // pass 2 (sweeps only): emit at the counted positions
+      if (!failed && logS > 0) {
+        publish();
+        __syncthreads();
+        for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
+          build(logS, sw);
+          if (misc[0]) { failed = true; reset(); break; }
+          emit();
+          reset();
+        }
       }
       if (!failed) break;
-      ++logS;
-      __syncthreads();
     }
+    if (threadIdx.x == 0) rec[b] = misc[4];
 
     // bucket totals -> window statistics 0..2
     block_sum_max(sum, mx, st.red);
     const uint32_t nlinks = block_sum(links, st.red);
     if (threadIdx.x == 0) {
-      u64* o = P->out + u64(W.out_index) * 9;
+      NSGC_GLOBAL u64* o = gptr(P->out) + u64(W.out_index) * 9;
       stat_add(o + 0, sum);
       stat_add(o + 1, nlinks);
       stat_max(o + 2, mx);
-      misc[3] = nlinks ? atomicAdd(&P->counters[W.counter], nlinks) : 0u;
     }
     __syncthreads();
-    const uint32_t base = misc[3];
-    block_exclusive_scan(histR, R, st.red);
-    block_exclusive_scan(histC, C, st.red);
-    uint32_t* rec = P->lbmeta + W.lbmeta + u64(b) * (R + C + 3);
-    if (threadIdx.x == 0) rec[0] = base;
-    for (uint32_t i = threadIdx.x; i <= R; i += NSGC_BLOCK) rec[1 + i] = histR[i];
-    for (uint32_t i = threadIdx.x; i <= C; i += NSGC_BLOCK) rec[R + 2 + i] = histC[i];
-    __syncthreads();
-
-    // emission: histR / histC now serve as per-bucket cursors
-    u64* erow = P->emit_row + W.ws + base;
-    u64* ecol = P->emit_col + W.ws + base;
-    for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
-      if (logS) build(logS, sw);  // a sweep that fit once fits again
-      for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
-        const u64 key = tk[i];
-        if (key != EMPTY64) {
-          const uint32_t c = tc[i];
-          const uint32_t s = uint32_t(key >> 32), d = uint32_t(key);
-          const uint32_t pr = lds_add(&histR[top32(row_hash(s), W.logR)], 1);
-          const uint32_t pc = lds_add(&histC[top32(col_hash(d), W.logC)], 1);
-          erow[pr] = (u64(s) << 32) | c;
-          ecol[pc] = (u64(d) << 32) | c;
-        }
-      }
-      if (threadIdx.x == 0 && misc[2]) {
-        const uint32_t c = misc[2];
-        const uint32_t pr = lds_add(&histR[top32(row_hash(EMPTY32), W.logR)], 1);
-        const uint32_t pc = lds_add(&histC[top32(col_hash(EMPTY32), W.logC)], 1);
-        erow[pr] = (u64(EMPTY32) << 32) | c;
-        ecol[pc] = (u64(EMPTY32) << 32) | c;
-      }
-      __syncthreads();
-    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Phase C: aggregation of one row bucket (or column bucket).
 //
-// Gathers the bucket's run from every link bucket's emission into an LDS table
-// id -> (packets, links); each entry is one link with its packet count, so the
-// table yields r(s) and f(s) (or c(d) and g(d)) for every id of the bucket.
-// Entries that repeat the first active lane's id are pre-combined with one
-// ballot and one DPP sum.  Overflow splits the bucket into sweeps as in B.
+// Gathers the bucket's (id, packets) entries -- one per link -- from every
+// link bucket into an LDS table id -> (packets, links): this yields r(s) and
+// f(s) (or c(d) and g(d)) for every id of the bucket, hence its share of
+// stats 3-5 (or 6-8).  Entries that repeat the first valid lane's id are
+// pre-combined with one ballot and one DPP sum.  As in phase B the occupied
+// slots are listed, and overflow splits the bucket into sweeps by id-hash
+// bits.
 // ---------------------------------------------------------------------------
 
 size_t lds_rc_bytes(uint32_t slots_log2) {
   const size_t S = size_t(1) << slots_log2;
-  return align16(S * 4) * 3 + align16(NSGC_MAX_SEG * 8) + align16((NSGC_MAX_SEG + 1) * 4) +
-         256;
+  return align16(S * 4) * 4 + align16(NSGC_MAX_SEG * 8) + align16((NSGC_MAX_SEG + 1) * 4) + 256;
 }
 
-__global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol(const nsgc_dev_plan* __restrict__ P) {
+__global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol(nsgc_dev_plan* P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t S = 1u << P->rc_slots_log2;
-  const uint32_t mask = S - 1;
-  const uint32_t limit = S - (S >> 2);
   unsigned char* p = smem;
   uint32_t* tk = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
-  uint32_t* tp = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
-  uint32_t* tl = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
+  uint32_t* ta = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
+  uint32_t* tb = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
+  uint32_t* occ = reinterpret_cast<uint32_t*>(p);      p += align16(S * 4);
   SegStage st;
   st.base = reinterpret_cast<u64*>(p);                 p += align16(NSGC_MAX_SEG * 8);
   st.off = reinterpret_cast<uint32_t*>(p);             p += align16((NSGC_MAX_SEG + 1) * 4);
-  uint32_t* misc = reinterpret_cast<uint32_t*>(p);     // [0] occupancy [1] overflow
-                                                       // [2,3] special id (packets, links)
+  uint32_t* misc = reinterpret_cast<uint32_t*>(p);     // [0] fail flag, [2,3] special id,
+                                                       // [5] occupied slots, [7] queue slot
   st.red = misc + 8;
 
+  for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
+    tk[i] = EMPTY32;
+    ta[i] = 0;
+    tb[i] = 0;
+  }
+  if (threadIdx.x == 0) misc[5] = 0;
+
   const uint32_t items = P->itemsC;
-  for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const uint32_t wi = owner_of(P->prefC, P->num_part, item);
-    const nsgc_win_desc W = P->win[wi];
-    const uint32_t k = item - P->prefC[wi];
-    const uint32_t B = 1u << W.logB, R = 1u << W.logR, C = 1u << W.logC;
+  ItemQueue q{gptr(&P->queue[2]), misc + 7, 0};
+  for (uint32_t item = q.first(items); item < items; item = q.next(items)) {
+    const uint32_t wi = owner_of_wave(gptr(P->prefC), P->num_part, item);
+    const nsgc_win_desc W = gload(P->win + wi);
+    const uint32_t k = item - gptr(P->prefC)[wi];
+    const uint32_t B = 1u << W.logB, R = 1u << W.logR;
     const bool is_row = k < R;
     const uint32_t bucket = is_row ? k : k - R;
     const uint32_t logK = is_row ? W.logR : W.logC;
-    const uint32_t stride = R + C + 3;
-    const uint32_t first_word = is_row ? 1 + bucket : R + 2 + bucket;
-    const uint32_t* recs = P->lbmeta + W.lbmeta;
-    const u64* em = (is_row ? P->emit_row : P->emit_col) + W.ws;
+    const NSGC_GLOBAL uint32_t* rec = gptr(P->lbmeta) + W.lbmeta;
+    const NSGC_GLOBAL uint32_t* st0 =
+        rec + B + (is_row ? u64(bucket) * B : u64(R + 1) * B + u64(bucket) * B);
+    const NSGC_GLOBAL uint32_t* st1 = st0 + B;
+    const NSGC_GLOBAL u64* em = gptr(is_row ? P->emit_row : P->emit_col) + W.ws;
 
     auto seg = [&](uint32_t lb, u64& base, uint32_t& len) {
-      const uint32_t* rec = recs + u64(lb) * stride;
-      const uint32_t s0 = rec[first_word], s1 = rec[first_word + 1];
-      base = u64(rec[0]) + s0;
+      const uint32_t s0 = st0[lb], s1 = st1[lb];
+      base = u64(rec[lb]) + s0;
       len = s1 - s0;
     };
 
-    auto build = [&](uint32_t logS, uint32_t sw) {
-      for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
-        tk[i] = EMPTY32;
-        tp[i] = 0;
-        tl[i] = 0;
+    auto reset = [&]() {
+      const uint32_t n = misc[5];
+      for (uint32_t i = threadIdx.x; i < n; i += NSGC_BLOCK) {
+        const uint32_t s = occ[i];
+        tk[s] = EMPTY32;
+        ta[s] = 0;
+        tb[s] = 0;
       }
+      __syncthreads();
+      if (threadIdx.x == 0) misc[5] = 0;
+      __syncthreads();
+    };
+
+    auto build = [&](uint32_t logS, uint32_t sw) {
       if (threadIdx.x < 4) misc[threadIdx.x] = 0;
       __syncthreads();
-      for_each_segment_element(B, st, seg, [&](u64 pos, bool valid) {
-        uint32_t id = 0, cnt = 0, h = 0;
-        if (valid) {
-          const u64 e = em[pos];
-          id = uint32_t(e >> 32);
-          cnt = uint32_t(e);
-          h = is_row ? row_hash(id) : col_hash(id);
-          if (logS && next32(h, logK, logS) != sw) valid = false;
+      gather_segments(B, st, seg, [&](const u64 (&pos)[U], const bool (&okin)[U]) {
+        uint32_t id[U], h[U], pk[U], ln[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const u64 e = okin[u] ? em[pos[u]] : 0ull;
+          id[u] = uint32_t(e >> 32);
+          pk[u] = uint32_t(e);
+          ln[u] = 1;
         }
-        if (valid && id == EMPTY32) {
-          lds_add(&misc[2], cnt);
-          lds_add(&misc[3], 1);
-          valid = false;
-        }
-        if (valid && lds_load(&misc[1])) valid = false;
-        const u64 vm = __ballot(valid);
-        if (!vm) return;
-        const int first = __ffsll(static_cast<unsigned long long>(vm)) - 1;
-        const uint32_t id0 = readlane(id, first);
-        const bool same = valid && id == id0;
-        const u64 sm = __ballot(same);
-        const uint32_t nsame = __popcll(sm);
-        uint32_t addp = cnt, addl = 1;
-        if (nsame > 1) {
-          const uint32_t tot = wave_sum(same ? cnt : 0u);
-          if (same) {
-            if (int(lane_id()) != first) valid = false;
-            else { addp = tot; addl = nsame; }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          h[u] = is_row ? row_hash(id[u]) : col_hash(id[u]);
+          ok[u] = okin[u] && !(logS && next32(h[u], logK, logS) != sw);
+          if (ok[u] && id[u] == EMPTY32) {
+            lds_add(&misc[2], pk[u]);
+            lds_add(&misc[3], 1);
+            ok[u] = false;
+          }
+          // combine the lanes holding the first valid lane's id
+          const u64 vm = __ballot(ok[u]);
+          if (vm) {
+            const int first = __ffsll(static_cast<unsigned long long>(vm)) - 1;
+            const uint32_t id0 = readlane(id[u], first);
+            const bool same = ok[u] && id[u] == id0;
+            const uint32_t nsame = __popcll(__ballot(same));
+            if (nsame > 1) {
+              const uint32_t tot = wave_sum(same ? pk[u] : 0u);
+              if (same) {
+                if (int(lane_id()) == first) { pk[u] = tot; ln[u] = nsame; }
+                else ok[u] = false;
+              }
+            }
           }
         }
-        if (valid) {
-          bool fresh;
-          const int slot = lds_insert32(tk, mask, id, h, fresh);
-          if (slot < 0) {
-            lds_store(&misc[1], 1);
-          } else {
-            if (fresh && lds_add(&misc[0], 1) >= limit) lds_store(&misc[1], 1);
-            lds_add(&tp[slot], addp);
-            lds_add(&tl[slot], addl);
+        int slot[U];
+        bool fresh[U];
+        if (!cas_insert<U>(tk, S - 1, id, h, ok, slot, fresh, NSGC_MAX_PROBES))
+          lds_store(&misc[0], 1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (slot[u] >= 0) {
+            lds_add(&ta[slot[u]], pk[u]);
+            lds_add(&tb[slot[u]], ln[u]);
           }
+          if (fresh[u]) occ[lds_add(&misc[5], 1)] = uint32_t(slot[u]);
         }
       });
     };
 
-    uint32_t logS = 0;
     uint32_t n = 0, mp = 0, ml = 0;
-    for (;;) {
+    for (uint32_t logS = 0;; ++logS) {
       n = mp = ml = 0;
       bool failed = false;
       for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
         build(logS, sw);
-        if (misc[1]) { failed = true; break; }
-        for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
-          if (tk[i] != EMPTY32) {
+        if (misc[0]) { failed = true; reset(); break; }
+        const uint32_t m = misc[5];
+        for (uint32_t i = threadIdx.x; i < m; i += NSGC_BLOCK) {
+          const uint32_t s = occ[i];
+          mp = max(mp, ta[s]);
+          ml = max(ml, tb[s]);
+        }
+        if (threadIdx.x == 0) {
+          n += m;
+          if (misc[3]) {
             ++n;
-            mp = max(mp, tp[i]);
-            ml = max(ml, tl[i]);
+            mp = max(mp, misc[2]);
+            ml = max(ml, misc[3]);
           }
         }
-        if (threadIdx.x == 0 && misc[3]) {
-          ++n;
-          mp = max(mp, misc[2]);
-          ml = max(ml, misc[3]);
-        }
-        __syncthreads();
+        reset();
       }
       if (!failed) break;
-      ++logS;
-      __syncthreads();
     }
     block_sum_max(n, mp, st.red);
     uint32_t zero = 0;
     block_sum_max(zero, ml, st.red);
     if (threadIdx.x == 0) {
-      u64* o = P->out + u64(W.out_index) * 9 + (is_row ? 3 : 6);
+      NSGC_GLOBAL u64* o = gptr(P->out) + u64(W.out_index) * 9 + (is_row ? 3 : 6);
       stat_add(o + 0, n);
       stat_max(o + 1, mp);
       stat_max(o + 2, ml);
@@ -571,17 +740,17 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol(const nsgc_dev_plan* __re
 // ---------------------------------------------------------------------------
 
 hipError_t launch_small(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_small, dim3(grid), dim3(NSGC_BLOCK), lds, s, P);
+  hipLaunchKernelGGL(k_small, dim3(grid), dim3(NSGC_BLOCK), lds, s, const_cast<nsgc_dev_plan*>(P));
   return hipGetLastError();
 }
 
-hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t grid, size_t lds,
-                            hipStream_t s) {
+hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t max_buckets,
+                            uint32_t grid, size_t lds, hipStream_t s) {
   switch (tile_log2) {
-    case 11: hipLaunchKernelGGL(k_partition<4>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P); break;
-    case 12: hipLaunchKernelGGL(k_partition<8>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P); break;
-    case 13: hipLaunchKernelGGL(k_partition<16>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P); break;
-    case 14: hipLaunchKernelGGL(k_partition<32>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P); break;
+    case 11: hipLaunchKernelGGL(k_partition<4>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_buckets); break;
+    case 12: hipLaunchKernelGGL(k_partition<8>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_buckets); break;
+    case 13: hipLaunchKernelGGL(k_partition<16>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_buckets); break;
+    case 14: hipLaunchKernelGGL(k_partition<32>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_buckets); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -589,27 +758,27 @@ hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t
 
 hipError_t launch_links(const nsgc_dev_plan* P, uint32_t max_buckets, uint32_t grid, size_t lds,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_links, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_buckets);
+  hipLaunchKernelGGL(k_links, dim3(grid), dim3(NSGC_BLOCK), lds, s, const_cast<nsgc_dev_plan*>(P),
+                     max_buckets);
   return hipGetLastError();
 }
 
 hipError_t launch_rowcol(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_rowcol, dim3(grid), dim3(NSGC_BLOCK), lds, s, P);
+  hipLaunchKernelGGL(k_rowcol, dim3(grid), dim3(NSGC_BLOCK), lds, s, const_cast<nsgc_dev_plan*>(P));
   return hipGetLastError();
 }
 
 hipError_t allow_large_lds(size_t bytes) {
-  hipError_t e;
   const int b = int(bytes);
-  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, b)) != hipSuccess)
-    return e;
-  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_links),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, b)) != hipSuccess)
-    return e;
-  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rowcol),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, b)) != hipSuccess)
-    return e;
+  const void* fns[] = {
+      reinterpret_cast<const void*>(&k_small),         reinterpret_cast<const void*>(&k_links),
+      reinterpret_cast<const void*>(&k_rowcol),        reinterpret_cast<const void*>(&k_partition<4>),
+      reinterpret_cast<const void*>(&k_partition<8>),  reinterpret_cast<const void*>(&k_partition<16>),
+      reinterpret_cast<const void*>(&k_partition<32>)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 

@@ -15,9 +15,9 @@
 //     B  link aggregation: one item per link bucket gathers its segments from
 //        every tile into an LDS hash table (key -> packet count).  This gives
 //        A's non-zeros: sum, count and max per bucket (stats 0-2).  The
-//        de-duplicated links are then emitted twice, as (src, count) grouped
-//        by row bucket and as (dst, count) grouped by column bucket, into a
-//        region reserved from the window's emission cursor.
+//        de-duplicated links are then emitted twice, as (src, packets) grouped
+//        by row bucket and as (dst, packets) grouped by column bucket, into
+//        the bucket's own emission region (as many slots as it has packets).
 //     C  row / column aggregation: one item per row bucket and per column
 //        bucket gathers its runs from every link bucket into an LDS table
 //        id -> (packets, links), giving stats 3-5 and 6-8.
@@ -29,7 +29,8 @@
 #include <stdint.h>
 
 #define NSGC_BLOCK 512          // threads per workgroup in every kernel
-#define NSGC_MAX_SEG 1024       // segments staged in LDS at a time (phases B, C)
+#define NSGC_MAX_SEG 512        // segments staged in LDS at a time (phases B, C)
+#define NSGC_UNROLL 8           // elements per thread in flight in the B/C gathers
 
 struct nsgc_small_desc {        // 16 bytes
   int64_t in_begin;             // index of the window's first packet
@@ -40,28 +41,36 @@ struct nsgc_small_desc {        // 16 bytes
 struct nsgc_win_desc {          // 64 bytes
   int64_t in_begin;             // index of the window's first packet
   int64_t ws;                   // element offset of the window in keys/emit arrays
-  int64_t tilemeta;             // u32 offset of the tile bucket starts [ntiles][B+1]
-  int64_t lbmeta;               // u32 offset of the link-bucket records [B][R+C+3]
+  int64_t tilemeta;             // u32 offset of the tile bucket starts [B+1][ntiles]
+  int64_t lbmeta;               // u32 offset of the link-bucket records (below)
   uint32_t n;                   // packets (< 2^32)
   uint32_t out_index;           // window index in out_stats
   uint32_t ntiles;              // partition tiles
-  uint32_t counter;             // index of the window's emission cursor
+  uint32_t counter;             // index of the window among partitioned windows
   uint8_t logB, logR, logC, pad0;
   uint32_t pad1[3];
 };
 
-// Link-bucket record (u32 words), stride R + C + 3:
-//   [0]                 emission base, relative to the window's ws offset
-//   [1 .. R+1]          row-bucket starts within the emission (R+1 entries)
-//   [R+2 .. R+C+2]      column-bucket starts within the emission (C+1 entries)
+// Tile bucket starts, bucket-major: word b * ntiles + t holds the number of
+// keys of tile t whose link bucket is < b (b = 0..B), so bucket b of tile t
+// is [start(b,t), start(b+1,t)) within the tile's region.  The emission
+// region of link bucket b starts at sum over t of start(b,t), the number of
+// the window's packets in buckets below b, and has one slot per packet of b.
+//
+// Link-bucket records of a window (u32 words), bucket-major so that a phase-C
+// item reads contiguous vectors over the link buckets b:
+//   [b]                                   emission base of link bucket b
+//   [B + r * B + b], r = 0..R             row-bucket r start in b's emission
+//   [B + (R+1) * B + c * B + b], c = 0..C column-bucket c start
+// A window's record block holds B * (R + C + 3) words.
 
 struct nsgc_dev_plan {          // header of the device plan buffer
   const uint32_t* src;
   const uint32_t* dst;
   unsigned long long* out;      // 9 x u64 per window
   unsigned long long* keys;     // partitioned packed keys
-  unsigned long long* emit_row; // (src << 32 | count) per link
-  unsigned long long* emit_col; // (dst << 32 | count) per link
+  unsigned long long* emit_row; // one entry per link: (src << 32 | packets)
+  unsigned long long* emit_col; // one entry per link: (dst << 32 | packets)
   uint32_t* tilemeta;
   uint32_t* lbmeta;
   uint32_t* counters;
@@ -78,6 +87,9 @@ struct nsgc_dev_plan {          // header of the device plan buffer
   uint32_t rc_slots_log2;
   uint32_t small_slots_log2;
   uint32_t pad[3];
+  // Work-queue counters of the small, B and C kernels (workgroups take items
+  // in order with an atomic increment).  Uploaded as zero with every plan.
+  uint32_t queue[4];
 };
 
 #endif  // NSGC_PLAN_H_

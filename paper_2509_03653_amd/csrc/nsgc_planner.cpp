@@ -36,7 +36,7 @@ void default_tune(nsgc_tune* t) {
 int check_tune(const nsgc_tune& t) {
   if (t.small_max < 0 || t.small_max > 2048) return NSGC_ERR_INVALID_ARG;
   if (t.tile_log2 < 11 || t.tile_log2 > 14) return NSGC_ERR_INVALID_ARG;
-  if (t.link_slots_log2 < 10 || t.link_slots_log2 > 13) return NSGC_ERR_INVALID_ARG;
+  if (t.link_slots_log2 < 10 || t.link_slots_log2 > 12) return NSGC_ERR_INVALID_ARG;
   if (t.rc_slots_log2 < 10 || t.rc_slots_log2 > 13) return NSGC_ERR_INVALID_ARG;
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16) return NSGC_ERR_INVALID_ARG;
   if (t.max_buckets_log2 < 0 || t.max_buckets_log2 > 12) return NSGC_ERR_INVALID_ARG;

@@ -52,6 +52,7 @@ int check_tune(const nsgc_tune& t);
 // Smallest k with 2^k >= x (x >= 1).
 int ceil_log2(uint64_t x);
 
+
 }  // namespace nsgc
 
 #endif  // NSGC_PLANNER_HPP_

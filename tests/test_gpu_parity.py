@@ -137,7 +137,7 @@ TUNES = {
     "tile_16k": dict(tile_log2=14),
     "one_bucket": dict(max_buckets_log2=0),
     "many_buckets": dict(cls=[[64, 64, 64]] * 33, max_buckets_log2=12),
-    "big_tables": dict(link_slots_log2=13, rc_slots_log2=13, blocks_per_cu=1),
+    "big_tables": dict(link_slots_log2=12, rc_slots_log2=13, blocks_per_cu=1),
 }
 
 
