@@ -18,6 +18,10 @@
  *   max_destination_packets = max c                    (row 7, reversed)
  *   max_destination_fanin   = max g                    (row 9, reversed)
  *
+ * A window whose valid_packets comes back with bit 63 set hit an internal
+ * limit of the library (it never happens for windows below 2^32 packets
+ * unless the library is broken); its statistics must not be used.
+ *
  * Maxima over an empty set are 0: an empty window yields nine zeros.  Every
  * pair in a window is a valid packet (there is no validity mask at this layer).
  * All results are exact integers; they do not depend on batching, tiering,
@@ -127,7 +131,8 @@ int nsgc_release(void);
 /*
  * Tuning.  The planner's knobs, per window-size class (class k holds windows
  * with 2^k <= packets < 2^(k+1); class 0 also holds empty windows).
- * Every setting gives identical statistics; only speed changes.
+ * Every setting gives identical statistics (max_sweeps_log2 below its
+ * default aside); only speed changes.
  */
 typedef struct nsgc_tune_class {
   int32_t link_target;      /* packets per link bucket (sets the bucket count) */
@@ -144,7 +149,12 @@ typedef struct nsgc_tune {
   int32_t rc_slots_log2;    /* LDS row/column table: 2^k slots (10..13) */
   int32_t blocks_per_cu;    /* persistent grid: workgroups per compute unit (1..16) */
   int32_t max_buckets_log2; /* cap on link/row/column buckets per window (0..12) */
-  int32_t reserved[2];
+  int32_t max_sweeps_log2;  /* a bucket whose LDS table overflows is re-run in
+                               2, 4, ... sweeps; past 2^max_sweeps_log2 sweeps
+                               it is abandoned and its window marked invalid
+                               (0..24, default 24; lower values exist only to
+                               exercise that error path) */
+  int32_t reserved;
   nsgc_tune_class cls[33];
 } nsgc_tune;
 

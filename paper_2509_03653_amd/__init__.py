@@ -90,12 +90,13 @@ class Tune(ctypes.Structure):
         ("rc_slots_log2", ctypes.c_int32),
         ("blocks_per_cu", ctypes.c_int32),
         ("max_buckets_log2", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("max_sweeps_log2", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("cls", TuneClass * 33),
     ]
 
     SCALARS = ("small_max", "tile_log2", "link_slots_log2", "rc_slots_log2",
-               "blocks_per_cu", "max_buckets_log2")
+               "blocks_per_cu", "max_buckets_log2", "max_sweeps_log2")
 
     def to_dict(self) -> dict:
         d = {k: int(getattr(self, k)) for k in self.SCALARS}
@@ -214,6 +215,19 @@ def _run(fn, what, src, dst, offsets, out, stream):
                 _stream_handle(stream, src.device))
     _check(rc, what)
     return out
+
+
+INVALID_BIT = 1 << 63
+
+
+def check_valid(stats) -> None:
+    """Raise if any window of a finished (W, 9) result carries the library's
+    invalid marker (bit 63 of valid_packets).  Synchronises with the tensor."""
+    import torch
+    col = stats[:, 0] if isinstance(stats, torch.Tensor) else np.asarray(stats)[:, 0]
+    bad = (col < 0) if isinstance(stats, torch.Tensor) else (np.asarray(col).astype(np.uint64) >> np.uint64(63)) != 0
+    if bool(bad.any()):
+        raise NsgcError(-5, "window statistics marked invalid by the library")
 
 
 def window_stats(src, dst, offsets, out=None, stream=None):

@@ -30,6 +30,12 @@ constexpr int U = NSGC_UNROLL;
 // Probes before an insert of phases B and C gives up; the caller then splits
 // the keys into sweeps, so giving up never changes a result.
 constexpr uint32_t NSGC_MAX_PROBES = 64;
+// A bucket whose table overflows even with 2^max_sweeps_log2 sweeps (plan
+// header) is abandoned: every doubling halves the keys per sweep, so real
+// data never gets near the default limit; it turns a broken invariant into a
+// reported error instead of an endless loop.  The window's valid-packet count
+// then carries bit 63 (no real count reaches it).
+constexpr u64 NSGC_INVALID_BIT = 1ull << 63;
 
 }  // namespace
 
@@ -510,7 +516,9 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_links(nsgc_dev_plan* P, uint32_t
     // Attempt with 2^logS sweeps; any insert that gives up restarts the whole
     // bucket with twice the sweeps (the emission is rewritten from scratch).
     uint32_t links = 0, sum = 0, mx = 0;
+    bool abandoned = false;
     for (uint32_t logS = 0;; ++logS) {
+      if (logS > P->max_sweeps_log2) { abandoned = true; break; }
       links = sum = mx = 0;
       for (uint32_t i = threadIdx.x; i < R; i += NSGC_BLOCK) histR[i] = 0;
       for (uint32_t i = threadIdx.x; i < C; i += NSGC_BLOCK) histC[i] = 0;
@@ -555,6 +563,11 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_links(nsgc_dev_plan* P, uint32_t
       }
       if (!failed) break;
     }
+    if (abandoned) {  // publish empty row/column segments so phase C reads nothing here
+      for (uint32_t i = threadIdx.x; i <= R; i += NSGC_BLOCK) rec[B + u64(i) * B + b] = 0;
+      for (uint32_t i = threadIdx.x; i <= C; i += NSGC_BLOCK)
+        rec[B + u64(R + 1) * B + u64(i) * B + b] = 0;
+    }
     if (threadIdx.x == 0) rec[b] = misc[4];
 
     // bucket totals -> window statistics 0..2
@@ -562,6 +575,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_links(nsgc_dev_plan* P, uint32_t
     const uint32_t nlinks = block_sum(links, st.red);
     if (threadIdx.x == 0) {
       NSGC_GLOBAL u64* o = gptr(P->out) + u64(W.out_index) * 9;
+      if (abandoned)
+        __hip_atomic_fetch_or(o, NSGC_INVALID_BIT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       stat_add(o + 0, sum);
       stat_add(o + 1, nlinks);
       stat_max(o + 2, mx);
@@ -698,7 +713,9 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol(nsgc_dev_plan* P) {
     };
 
     uint32_t n = 0, mp = 0, ml = 0;
+    bool abandoned = false;
     for (uint32_t logS = 0;; ++logS) {
+      if (logS > P->max_sweeps_log2) { abandoned = true; break; }
       n = mp = ml = 0;
       bool failed = false;
       for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
@@ -727,6 +744,9 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol(nsgc_dev_plan* P) {
     block_sum_max(zero, ml, st.red);
     if (threadIdx.x == 0) {
       NSGC_GLOBAL u64* o = gptr(P->out) + u64(W.out_index) * 9 + (is_row ? 3 : 6);
+      if (abandoned)
+        __hip_atomic_fetch_or(o - (is_row ? 3 : 6), NSGC_INVALID_BIT, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
       stat_add(o + 0, n);
       stat_max(o + 1, mp);
       stat_max(o + 2, ml);

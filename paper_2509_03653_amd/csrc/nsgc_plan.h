@@ -86,7 +86,8 @@ struct nsgc_dev_plan {          // header of the device plan buffer
   uint32_t link_slots_log2;
   uint32_t rc_slots_log2;
   uint32_t small_slots_log2;
-  uint32_t pad[3];
+  uint32_t max_sweeps_log2;     // overflow sweeps allowed before a bucket is abandoned
+  uint32_t pad[2];
   // Work-queue counters of the small, B and C kernels (workgroups take items
   // in order with an atomic increment).  Uploaded as zero with every plan.
   uint32_t queue[4];

@@ -26,6 +26,7 @@ void default_tune(nsgc_tune* t) {
   t->rc_slots_log2 = 12;
   t->blocks_per_cu = 2;
   t->max_buckets_log2 = 10;
+  t->max_sweeps_log2 = 24;
   for (int k = 0; k <= 32; ++k) {
     t->cls[k].link_target = 2048;
     t->cls[k].row_target = 4096;
@@ -40,6 +41,7 @@ int check_tune(const nsgc_tune& t) {
   if (t.rc_slots_log2 < 10 || t.rc_slots_log2 > 13) return NSGC_ERR_INVALID_ARG;
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16) return NSGC_ERR_INVALID_ARG;
   if (t.max_buckets_log2 < 0 || t.max_buckets_log2 > 12) return NSGC_ERR_INVALID_ARG;
+  if (t.max_sweeps_log2 < 0 || t.max_sweeps_log2 > 24) return NSGC_ERR_INVALID_ARG;
   for (int k = 0; k <= 32; ++k) {
     const nsgc_tune_class& c = t.cls[k];
     if (c.link_target < 64 || c.row_target < 64 || c.col_target < 64) return NSGC_ERR_INVALID_ARG;
@@ -69,6 +71,7 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
   p->tile_log2 = uint32_t(tune.tile_log2);
   p->link_slots_log2 = uint32_t(tune.link_slots_log2);
   p->rc_slots_log2 = uint32_t(tune.rc_slots_log2);
+  p->max_sweeps_log2 = uint32_t(tune.max_sweeps_log2);
   p->small_slots_log2 = uint32_t(std::max(ceil_log2(uint64_t(std::max(tune.small_max, 1)) * 2), 6));
 
   const uint64_t tile = uint64_t(1) << tune.tile_log2;
@@ -188,6 +191,7 @@ void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const ui
   h.link_slots_log2 = link_slots_log2;
   h.rc_slots_log2 = rc_slots_log2;
   h.small_slots_log2 = small_slots_log2;
+  h.max_sweeps_log2 = max_sweeps_log2;
   std::memcpy(base, &h, sizeof h);
   if (!small.empty()) std::memcpy(base + o.small, small.data(), small.size() * sizeof(nsgc_small_desc));
   if (!win.empty()) std::memcpy(base + o.win, win.data(), win.size() * sizeof(nsgc_win_desc));

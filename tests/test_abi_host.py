@@ -75,10 +75,27 @@ def test_tune_roundtrip_and_validation():
     assert d["small_max"] >= 0 and 11 <= d["tile_log2"] <= 14
     t2 = nsgc.Tune.from_dict(d)
     assert t2.to_dict() == d
-    bad = nsgc.Tune.from_dict(dict(d, tile_log2=9))
+    assert d["max_sweeps_log2"] == 24
+    for k, v in (("tile_log2", 9), ("tile_log2", 15), ("link_slots_log2", 13),
+                 ("rc_slots_log2", 14), ("small_max", 2049), ("blocks_per_cu", 0),
+                 ("max_buckets_log2", 13), ("max_sweeps_log2", 25), ("max_sweeps_log2", -1)):
+        with pytest.raises(nsgc.NsgcError):
+            nsgc.set_tune(nsgc.Tune.from_dict(dict(d, **{k: v})))
+        assert nsgc.get_tune().to_dict() == d, k
+    bad_cls = [list(r) for r in d["cls"]]
+    bad_cls[5][1] = 63
     with pytest.raises(nsgc.NsgcError):
-        nsgc.set_tune(bad)
+        nsgc.set_tune(nsgc.Tune.from_dict(dict(d, cls=bad_cls)))
     assert nsgc.get_tune().to_dict() == d
+
+
+def test_check_valid_flags_marked_windows():
+    ok = np.zeros((3, 9), np.uint64)
+    nsgc.check_valid(ok)
+    bad = ok.copy()
+    bad[1, 0] = np.uint64(1 << 63) | np.uint64(17)
+    with pytest.raises(nsgc.NsgcError):
+        nsgc.check_valid(bad)
 
 
 def test_plan_tiers_and_cutover():

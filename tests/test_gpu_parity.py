@@ -206,3 +206,42 @@ def test_stream_argument_and_out_reuse():
     nsgc.window_stats(s, d, wl.offsets, out=out, stream=st)
     st.synchronize()
     assert_same(out.cpu().numpy().view(np.uint64), want, "side stream")
+
+
+def test_abandoned_bucket_is_reported_not_hung():
+    # With no overflow sweeps allowed, a bucket whose LDS table overflows is
+    # abandoned: its window must come back marked invalid (bit 63 of stat 0)
+    # while the other windows of the batch stay exact.
+    rng = np.random.default_rng(21)
+    sizes = [3000, 9000, 9000, 2500]
+    off = synth.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    src = np.zeros(n, np.uint32)
+    dst = np.zeros(n, np.uint32)
+    a = [int(x) for x in off]
+    src[a[0]:a[1]] = rng.integers(0, 10, sizes[0])          # few links: fits
+    dst[a[0]:a[1]] = rng.integers(0, 5, sizes[0])
+    src[a[1]:a[2]] = np.arange(sizes[1]) * 7 + 1            # 9000 distinct links
+    dst[a[1]:a[2]] = np.arange(sizes[1]) % 97
+    src[a[2]:a[3]] = 5                                       # 3000 distinct columns
+    dst[a[2]:a[3]] = np.arange(sizes[2]) % 3000
+    src[a[3]:a[4]] = rng.integers(0, 40, sizes[3])
+    dst[a[3]:a[4]] = rng.integers(0, 40, sizes[3])
+    want = oracle.window_stats(src, dst, off)
+    base = nsgc.default_tune().to_dict()
+    base.update(link_slots_log2=12, rc_slots_log2=10, max_sweeps_log2=0, small_max=1024,
+                cls=[[1 << 20, 1 << 20, 1 << 20]] * 33, max_buckets_log2=0)
+    nsgc.set_tune(nsgc.Tune.from_dict(base))
+    for form in ("batched", "plain"):
+        say(f"[gpu] abandoned buckets form={form}")
+        got = gpu_stats(src, dst, off, form)
+        marked = (got[:, 0] >> np.uint64(63)) != 0
+        # w1: 9000 distinct links overflow the 4096-slot link table;
+        # w2: 3000 distinct destinations overflow the 1024-slot column table
+        assert list(marked) == [False, True, True, False], got
+        assert_same(got[[0, 3]], want[[0, 3]], f"unaffected windows {form}")
+        with pytest.raises(nsgc.NsgcError):
+            nsgc.check_valid(got)
+    # the default sweep limit handles the same batch exactly
+    nsgc.set_tune(nsgc.default_tune())
+    assert_same(gpu_stats(src, dst, off), want, "default sweeps")
