@@ -154,7 +154,13 @@ typedef struct nsgc_tune {
                                it is abandoned and its window marked invalid
                                (0..24, default 24; lower values exist only to
                                exercise that error path) */
-  int32_t reserved;
+  int32_t combine_probes;   /* 0 (default): phase B emits one row and one
+                               column entry per link.  1..64: it first combines
+                               the bucket's links per source and destination
+                               in LDS (one entry per id and link bucket; pays
+                               off when single sources or destinations own a
+                               large share of the links), with this probe
+                               limit before falling back to per-link entries */
   nsgc_tune_class cls[33];
 } nsgc_tune;
 

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "nsgc.h"
@@ -20,14 +21,15 @@ namespace nsgc {
 hipError_t launch_small(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
 hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t max_buckets,
                             uint32_t grid, size_t lds, hipStream_t s);
-hipError_t launch_links(const nsgc_dev_plan* P, uint32_t max_buckets, uint32_t grid, size_t lds,
-                        hipStream_t s);
+hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_buckets, uint32_t grid,
+                        size_t lds, hipStream_t s);
 hipError_t launch_rowcol(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
 size_t lds_small_bytes(uint32_t slots_log2);
 size_t lds_part_bytes(uint32_t max_buckets, uint32_t tile_log2);
 size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_buckets);
 size_t lds_rc_bytes(uint32_t slots_log2);
 hipError_t allow_large_lds(size_t bytes);
+hipError_t resident_blocks(int which, uint32_t tile_log2, size_t lds, int* blocks);
 }  // namespace nsgc
 
 using namespace nsgc;
@@ -68,6 +70,8 @@ struct DevCtx {
   int cus = 256;
   size_t lds_limit = 65536;
   std::map<hipStream_t, Slot*> slots;
+  // resident workgroups per CU by (kernel, tile_log2, dynamic LDS bytes)
+  std::map<std::tuple<int, uint32_t, size_t>, int> resident;
 };
 
 std::mutex g_mu;
@@ -164,27 +168,48 @@ int take_stage(Slot* sl, size_t need, hipStream_t s, int* idx) {
 }
 
 struct Launch {
-  uint32_t grid_cap;
+  uint32_t grid_small, grid_part, grid_link, grid_rc;  // persistent grid of each kernel
+  bool combine;                                        // phase-B emission combines per id
   size_t lds_small, lds_part, lds_link, lds_rc;
   uint32_t max_buckets;
 };
 
-Launch launch_params(const DevCtx* c, const nsgc_tune& t) {
+// Workgroups per CU that can actually be resident (registers and LDS), at
+// most `want`: persistent workgroups beyond that would only queue.
+int resident_cap(DevCtx* c, int which, uint32_t tile_log2, size_t lds, int want, uint32_t* grid) {
+  const auto key = std::make_tuple(which, tile_log2, lds);
+  auto it = c->resident.find(key);
+  if (it == c->resident.end()) {
+    int n = 0;
+    NSGC_HIP(resident_blocks(which, tile_log2, lds, &n));
+    it = c->resident.emplace(key, std::max(n, 1)).first;
+  }
+  *grid = uint32_t(c->cus) * uint32_t(std::min(want, it->second));
+  return NSGC_OK;
+}
+
+int launch_params(DevCtx* c, const nsgc_tune& t, Launch* out) {
   Launch L;
-  L.grid_cap = uint32_t(c->cus) * uint32_t(t.blocks_per_cu);
   L.max_buckets = 1u << t.max_buckets_log2;
   const uint32_t small_log2 =
       uint32_t(std::max(ceil_log2(uint64_t(std::max(t.small_max, 1)) * 2), 6));
+  const uint32_t tile = uint32_t(t.tile_log2);
   L.lds_small = lds_small_bytes(small_log2);
-  L.lds_part = lds_part_bytes(L.max_buckets, uint32_t(t.tile_log2));
+  L.lds_part = lds_part_bytes(L.max_buckets, tile);
   L.lds_link = lds_link_bytes(uint32_t(t.link_slots_log2), L.max_buckets);
   L.lds_rc = lds_rc_bytes(uint32_t(t.rc_slots_log2));
-  return L;
-}
-
-int check_lds(const DevCtx* c, const Launch& L) {
   const size_t m = std::max(std::max(L.lds_small, L.lds_part), std::max(L.lds_link, L.lds_rc));
-  return m <= c->lds_limit ? NSGC_OK : NSGC_ERR_INVALID_ARG;
+  if (m > c->lds_limit) return NSGC_ERR_INVALID_ARG;
+  int rc;
+  const int want = t.blocks_per_cu;
+  if ((rc = resident_cap(c, 0, tile, L.lds_small, want, &L.grid_small)) != NSGC_OK) return rc;
+  if ((rc = resident_cap(c, 1, tile, L.lds_part, want, &L.grid_part)) != NSGC_OK) return rc;
+  L.combine = t.combine_probes > 0;
+  if ((rc = resident_cap(c, L.combine ? 4 : 2, tile, L.lds_link, want, &L.grid_link)) != NSGC_OK)
+    return rc;
+  if ((rc = resident_cap(c, 3, tile, L.lds_rc, want, &L.grid_rc)) != NSGC_OK) return rc;
+  *out = L;
+  return NSGC_OK;
 }
 
 // Which kernels a plan needs: bit 0 the small-window kernel, bit 1 phases A-C.
@@ -199,19 +224,23 @@ int plan_variant(const HostPlan& hp) {
 int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch& L,
                     uint32_t tile_log2, hipStream_t s, bool fixed_grid, int variant,
                     const hipEvent_t* ev = nullptr) {
-  auto grid = [&](uint32_t items) { return fixed_grid ? L.grid_cap : std::min(items, L.grid_cap); };
+  auto grid = [&](uint32_t items, uint32_t cap) { return fixed_grid ? cap : std::min(items, cap); };
   auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
   const bool small = fixed_grid ? (variant & 1) != 0 : !hp.small.empty();
   const bool part = fixed_grid ? (variant & 2) != 0 : !hp.win.empty();
   NSGC_HIP(mark(0));
-  if (small) NSGC_HIP(launch_small(dplan, grid(uint32_t(hp.small.size())), L.lds_small, s));
+  if (small)
+    NSGC_HIP(launch_small(dplan, grid(uint32_t(hp.small.size()), L.grid_small), L.lds_small, s));
   NSGC_HIP(mark(1));
   if (part)
-    NSGC_HIP(launch_partition(dplan, tile_log2, L.max_buckets, grid(hp.itemsA), L.lds_part, s));
+    NSGC_HIP(launch_partition(dplan, tile_log2, L.max_buckets, grid(hp.itemsA, L.grid_part),
+                              L.lds_part, s));
   NSGC_HIP(mark(2));
-  if (part) NSGC_HIP(launch_links(dplan, L.max_buckets, grid(hp.itemsB), L.lds_link, s));
+  if (part)
+    NSGC_HIP(launch_links(dplan, L.combine, L.max_buckets, grid(hp.itemsB, L.grid_link),
+                          L.lds_link, s));
   NSGC_HIP(mark(3));
-  if (part) NSGC_HIP(launch_rowcol(dplan, grid(hp.itemsC), L.lds_rc, s));
+  if (part) NSGC_HIP(launch_rowcol(dplan, grid(hp.itemsC, L.grid_rc), L.lds_rc, s));
   NSGC_HIP(mark(4));
   return NSGC_OK;
 }
@@ -243,8 +272,8 @@ int get_slot(DevCtx* c, hipStream_t s, Slot** out) {
 // Upload one plan into slot `sl` and launch it.
 int run_plan(DevCtx* c, Slot* sl, const HostPlan& hp, const nsgc_tune& t, const uint32_t* src,
              const uint32_t* dst, void* out, hipStream_t s, const hipEvent_t* ev = nullptr) {
-  const Launch L = launch_params(c, t);
-  int rc = check_lds(c, L);
+  Launch L;
+  int rc = launch_params(c, t, &L);
   if (rc != NSGC_OK) return rc;
   const size_t pbytes = hp.plan_bytes();
   const WsLayout lay = hp.layout();
@@ -360,8 +389,8 @@ int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
   const hipStream_t s = static_cast<hipStream_t>(stream);
   Slot* sl = nullptr;
   if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
-  const Launch L = launch_params(c, t);
-  if ((rc = check_lds(c, L)) != NSGC_OK) return rc;
+  Launch L;
+  if ((rc = launch_params(c, t, &L)) != NSGC_OK) return rc;
 
   // One plan per window, all uploaded with one copy; the windows then run one
   // launch sequence each, in order, sharing one workspace.
@@ -576,10 +605,9 @@ int nsgc_graph_create(int64_t max_packets, int64_t max_windows, nsgc_graph** out
   nsgc_graph* g = new nsgc_graph;
   g->device = c->device;
   g->tune = current_tune();
-  g->L = launch_params(c, g->tune);
   g->max_packets = max_packets;
   g->max_windows = max_windows;
-  if ((rc = check_lds(c, g->L)) != NSGC_OK) {
+  if ((rc = launch_params(c, g->tune, &g->L)) != NSGC_OK) {
     destroy_graph(g);
     return rc;
   }

@@ -109,6 +109,26 @@ __device__ __forceinline__ uint32_t readlane(uint32_t v, int lane) {
   return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), lane));
 }
 
+// Set bits of `m` below the calling lane.
+__device__ __forceinline__ uint32_t rank_below(u64 m) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+}
+
+// Append the lanes with `want` to a list whose length is the LDS word *len:
+// one atomic per wavefront instead of one per lane (LDS atomics on a single
+// address are processed one lane at a time), each lane gets base + rank.
+// Call with the whole wavefront active; the result is defined where `want`.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* len, bool want) {
+  const u64 m = __ballot(want);
+  if (m == 0) return 0;
+  const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+  uint32_t base = 0;
+  if (int(lane_id()) == leader)
+    base = __hip_atomic_fetch_add(len, uint32_t(__popcll(m)), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+  return readlane(base, leader) + rank_below(m);
+}
+
 // Sum over all 64 lanes (call with the whole wavefront active).  Row-local
 // inclusive scan by DPP row shifts, then the four row totals by readlane.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -422,6 +442,10 @@ __device__ __forceinline__ void lockstep_owner(const uint32_t* off, uint32_t cn,
 
 __device__ __forceinline__ uint32_t lds_add(uint32_t* p, uint32_t v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t lds_sub(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ uint32_t lds_load(const uint32_t* p) {

@@ -6,16 +6,19 @@
 // matrix cores are used: the work is hashing, LDS aggregation and
 // order-independent integer reductions, bound by memory and LDS latency.
 //
-// Latency is the enemy here, so every per-element loop works on NSGC_UNROLL
-// elements per thread in lockstep: segment searches, global loads and LDS
-// compare-and-swap probes of the U elements are issued together and their
-// round trips overlap.
+// Latency is the enemy here, so every per-element loop works on up to
+// NSGC_UNROLL elements per thread in lockstep: segment searches, global loads
+// and LDS compare-and-swap probes of those elements are issued together and
+// their round trips overlap.  Each round takes the smallest unroll that
+// covers the elements left, so short items do not pay for idle slots.
 //
 // The kernels that take uneven items (small windows, phases B and C) draw them
 // from an atomic work queue; the partition kernel strides over its uniform
 // tiles.  Grids are persistent, so a captured graph replays any batch that
 // fits its workspace.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "nsgc_device.hpp"
 #include "nsgc_plan.h"
@@ -27,6 +30,41 @@ namespace {
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 constexpr int U = NSGC_UNROLL;
+static_assert(U == 8, "for_rounds dispatches U = 8, 4, 2, 1");
+
+template <class A>
+__host__ __device__ constexpr int array_len() {
+  return int(std::extent<std::remove_reference_t<A>>::value);
+}
+
+// Visits element indices [0, total) in rounds of UU * NSGC_BLOCK, calling
+// body(j0, integral_constant<int, UU>) with the smallest UU of 8, 4, 2, 1 that
+// covers what is left (UU = MAXU while more remains), so a short item does not
+// pay for idle slots.  MAXU bounds the registers a round holds.  `total` must
+// be uniform across the workgroup.
+template <int MAXU = U, class Body>
+__device__ __forceinline__ void for_rounds(uint32_t total, Body&& body) {
+  static_assert(MAXU == 8 || MAXU == 4 || MAXU == 2 || MAXU == 1, "unroll");
+  for (uint32_t j0 = 0; j0 < total;) {
+    const uint32_t rem = total - j0;
+    if (MAXU == 1 || (MAXU == 2 && rem > NSGC_BLOCK)) {
+      body(j0, std::integral_constant<int, MAXU>());
+      j0 += MAXU * NSGC_BLOCK;
+    } else if (MAXU == 8 && rem > 4 * NSGC_BLOCK) {
+      body(j0, std::integral_constant<int, 8>());
+      j0 += 8 * NSGC_BLOCK;
+    } else if (MAXU >= 4 && rem > 2 * NSGC_BLOCK) {
+      body(j0, std::integral_constant<int, (MAXU >= 4 ? 4 : 1)>());
+      j0 += 4 * NSGC_BLOCK;
+    } else if (rem > NSGC_BLOCK) {
+      body(j0, std::integral_constant<int, 2>());
+      j0 += 2 * NSGC_BLOCK;
+    } else {
+      body(j0, std::integral_constant<int, 1>());
+      j0 += NSGC_BLOCK;
+    }
+  }
+}
 // Probes before an insert of phases B and C gives up; the caller then splits
 // the keys into sweeps, so giving up never changes a result.
 constexpr uint32_t NSGC_MAX_PROBES = 64;
@@ -36,6 +74,40 @@ constexpr uint32_t NSGC_MAX_PROBES = 64;
 // reported error instead of an endless loop.  The window's valid-packet count
 // then carries bit 63 (no real count reaches it).
 constexpr u64 NSGC_INVALID_BIT = 1ull << 63;
+// Phase B holds 64-bit keys; four elements per thread keep it within 128
+// VGPRs, i.e. two 512-thread workgroups per compute unit.
+constexpr int LINK_MAXU = 4;
+constexpr int RC_MAXU = 4;
+// Links a thread holds while phase B combines them per source and
+// destination: the link table has at most LK * NSGC_BLOCK slots.
+constexpr int LK = 8;
+
+constexpr uint32_t ENT_PMAX = (1u << NSGC_ENT_PACKET_BITS) - 1;
+constexpr uint32_t ENT_LMAX = (1u << NSGC_ENT_LINK_BITS) - 1;
+static_assert(NSGC_ENT_PACKET_BITS + NSGC_ENT_LINK_BITS == 32, "entry fields");
+static_assert(LK * NSGC_BLOCK <= ENT_LMAX, "a bucket's links fit the link field");
+
+// Entries needed for an (id, links, packets) triple (1 <= links <= packets).
+__device__ __forceinline__ uint32_t entry_parts(uint32_t packets, uint32_t links) {
+  const uint32_t a = packets / ENT_PMAX + (packets % ENT_PMAX != 0);
+  const uint32_t b = links / ENT_LMAX + (links % ENT_LMAX != 0);
+  return max(max(a, b), 1u);
+}
+
+// Write the `parts` entries of a triple at e[at], e[at + 1], ...
+__device__ __forceinline__ void write_entry(NSGC_GLOBAL u64* e, uint32_t at, uint32_t id,
+                                            uint32_t packets, uint32_t links, uint32_t parts) {
+  if (parts == 1) {
+    e[at] = (u64(id) << 32) | (u64(links) << NSGC_ENT_PACKET_BITS) | packets;
+    return;
+  }
+  const uint32_t pq = packets / parts, pr = packets % parts;
+  const uint32_t lq = links / parts, lr = links % parts;
+  for (uint32_t i = 0; i < parts; ++i) {
+    const uint32_t p = pq + (i < pr), l = lq + (i < lr);
+    e[at + i] = (u64(id) << 32) | (u64(l) << NSGC_ENT_PACKET_BITS) | p;
+  }
+}
 
 }  // namespace
 
@@ -88,7 +160,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
 
     const NSGC_GLOBAL uint32_t* src = gptr(P->src) + D.in_begin;
     const NSGC_GLOBAL uint32_t* dst = gptr(P->dst) + D.in_begin;
-    for (uint32_t j0 = 0; j0 < D.n; j0 += U * NSGC_BLOCK) {
+    for_rounds(D.n, [&](uint32_t j0, auto uc) {
+      constexpr int U = decltype(uc)::value;
       uint32_t s[U], d[U], h[U];
       u64 key[U];
       bool ok[U], fresh[U], tab[U], rt[U];
@@ -152,7 +225,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
           if (fresh[u]) lds_add(&cf[slot[u]], 1);
         }
       }
-    }
+    });
     __syncthreads();
 
     uint32_t nl = 0, sl = 0, ml = 0, nr = 0, mr = 0, mf = 0, nc = 0, mc = 0, mg = 0;
@@ -224,7 +297,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* _
     const NSGC_GLOBAL uint32_t* src = gptr(P->src) + gbeg;
     const NSGC_GLOBAL uint32_t* dst = gptr(P->dst) + gbeg;
     u64 key[PER];
-    uint32_t bk[PER], rk[PER];
+    uint32_t br[PER];   // rank in bucket << 12 | bucket (buckets <= 4096, ranks < 2^14)
     bool ok[PER];
     const bool aligned = ((reinterpret_cast<uintptr_t>(P->src + gbeg) |
                            reinterpret_cast<uintptr_t>(P->dst + gbeg)) & 15) == 0;
@@ -252,15 +325,15 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* _
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       if (ok[k]) {
-        bk[k] = top64(link_hash(key[k]), W.logB);
-        rk[k] = lds_add(&hist[bk[k]], 1);
+        const uint32_t bk = top64(link_hash(key[k]), W.logB);
+        br[k] = (lds_add(&hist[bk], 1) << 12) | bk;
       }
     }
     __syncthreads();
     block_exclusive_scan(hist, B, red);
 #pragma unroll
     for (int k = 0; k < PER; ++k)
-      if (ok[k]) stage[hist[bk[k]] + rk[k]] = key[k];
+      if (ok[k]) stage[hist[br[k] & 0xFFFu] + (br[k] >> 12)] = key[k];
     NSGC_GLOBAL uint32_t* tm = gptr(P->tilemeta) + W.tilemeta + t;
     for (uint32_t i = threadIdx.x; i <= B; i += NSGC_BLOCK) tm[u64(i) * W.ntiles] = hist[i];
     __syncthreads();
@@ -272,9 +345,10 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* _
 
 // ---------------------------------------------------------------------------
 // Shared machinery of phases B and C: visit the elements of up to
-// NSGC_MAX_SEG segments at a time, U per thread per round.  `seg(i, base,
-// len)` describes segment i; `fn(pos, ok)` receives the U flat positions
-// (pos[u] valid when ok[u]) with the whole wavefront active.
+// NSGC_MAX_SEG segments at a time, up to U per thread per round.  `seg(i,
+// base, len)` describes segment i; `fn(pos, ok)` receives arrays of the
+// round's flat positions (pos[u] valid when ok[u]; the array length is the
+// round's unroll) with the whole wavefront active.
 // ---------------------------------------------------------------------------
 
 struct SegStage {
@@ -283,7 +357,7 @@ struct SegStage {
   uint32_t* red;   // [2 * WAVES]
 };
 
-template <class SegFn, class BatchFn>
+template <int MAXU, class SegFn, class BatchFn>
 __device__ __forceinline__ void gather_segments(uint32_t nseg, const SegStage& st, SegFn seg,
                                                 BatchFn fn) {
   for (uint32_t c0 = 0; c0 < nseg; c0 += NSGC_MAX_SEG) {
@@ -297,7 +371,8 @@ __device__ __forceinline__ void gather_segments(uint32_t nseg, const SegStage& s
     }
     __syncthreads();
     const uint32_t total = block_exclusive_scan(st.off, cn, st.red);
-    for (uint32_t j0 = 0; j0 < total; j0 += U * NSGC_BLOCK) {
+    for_rounds<MAXU>(total, [&](uint32_t j0, auto uc) {
+      constexpr int U = decltype(uc)::value;
       uint32_t j[U], idx[U];
       bool ok[U];
       u64 pos[U];
@@ -311,7 +386,7 @@ __device__ __forceinline__ void gather_segments(uint32_t nseg, const SegStage& s
 #pragma unroll
       for (int u = 0; u < U; ++u) pos[u] = st.base[idx[u]] + (j[u] - st.off[idx[u]]);
       fn(pos, ok);
-    }
+    });
     __syncthreads();
   }
 }
@@ -325,14 +400,19 @@ __device__ __forceinline__ void gather_segments(uint32_t nseg, const SegStage& s
 // one LDS address).  Every newly inserted slot is also appended to a list of
 // occupied slots, so everything after the inserts (statistics, emission and
 // resetting the table for the next item) costs per link, not per slot.  The
-// table gives the bucket's share of stats 0-2; its links are emitted as
-// (src, packets) grouped by row bucket and (dst, packets) grouped by column
-// bucket into the bucket's emission region.
+// table gives the bucket's share of stats 0-2.  Its links are then combined
+// per source and per destination in the same LDS region and emitted as
+// (src, packets, links) grouped by row bucket and (dst, packets, links)
+// grouped by column bucket into the bucket's emission region, so phase C
+// receives one entry per (link bucket, id) instead of one per link: a source
+// with thousands of links no longer makes one row bucket many times larger
+// than the others.
 //
 // If an insert gives up (more distinct keys than the table holds), the bucket
 // is split into 2^s sweeps by further hash bits and redone; the sweeps
 // partition the keys, so the result is unchanged.  With sweeps, every sweep
-// emits its own links, counted in a first pass and written in a second.
+// emits its own links uncombined (links = 1), counted in a first pass and
+// written in a second.
 // ---------------------------------------------------------------------------
 
 size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_buckets) {
@@ -341,7 +421,13 @@ size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_buckets) {
          align16((NSGC_MAX_SEG + 1) * 4) + 2 * align16((max_buckets + 1) * 4) + 256;
 }
 
-__global__ __launch_bounds__(NSGC_BLOCK) void k_links(nsgc_dev_plan* P, uint32_t max_buckets) {
+// COMBINE selects the single-sweep emission: per link (false) or combined per
+// source and destination (true, plan field combine_probes > 0); they are
+// separate instantiations so the per-link kernel carries none of the
+// combining code's registers.
+template <bool COMBINE>
+__global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_links(
+    nsgc_dev_plan* P, uint32_t max_buckets) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t S = 1u << P->link_slots_log2;
   unsigned char* p = smem;
@@ -411,7 +497,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_links(nsgc_dev_plan* P, uint32_t
     auto build = [&](uint32_t logS, uint32_t sw) {
       if (threadIdx.x < 2) misc[threadIdx.x] = 0;
       __syncthreads();
-      gather_segments(nt, st, seg, [&](const u64 (&pos)[U], const bool (&okin)[U]) {
+      gather_segments<LINK_MAXU>(nt, st, seg, [&](const auto& pos, const auto& okin) {
+        constexpr int U = array_len<decltype(pos)>();
         u64 key[U];
         uint32_t h[U], add[U];
         bool ok[U];
@@ -448,7 +535,11 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_links(nsgc_dev_plan* P, uint32_t
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (slot[u] >= 0) lds_add(&tc[slot[u]], add[u]);
-          if (fresh[u]) occ[lds_add(&misc[5], 1)] = uint32_t(slot[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t at = wave_append(&misc[5], fresh[u]);
+          if (fresh[u]) occ[at] = uint32_t(slot[u]);
         }
       });
     };
@@ -457,13 +548,16 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_links(nsgc_dev_plan* P, uint32_t
     auto count = [&]() {
       const uint32_t n = misc[5];
       for (uint32_t i = threadIdx.x; i < n; i += NSGC_BLOCK) {
-        const u64 key = tk[occ[i]];
-        lds_add(&histR[top32(row_hash(uint32_t(key >> 32)), W.logR)], 1);
-        lds_add(&histC[top32(col_hash(uint32_t(key)), W.logC)], 1);
+        const uint32_t s = occ[i];
+        const u64 key = tk[s];
+        const uint32_t parts = entry_parts(tc[s], 1);
+        lds_add(&histR[top32(row_hash(uint32_t(key >> 32)), W.logR)], parts);
+        lds_add(&histC[top32(col_hash(uint32_t(key)), W.logC)], parts);
       }
       if (threadIdx.x == 0 && misc[1]) {
-        lds_add(&histR[top32(row_hash(EMPTY32), W.logR)], 1);
-        lds_add(&histC[top32(col_hash(EMPTY32), W.logC)], 1);
+        const uint32_t parts = entry_parts(misc[1], 1);
+        lds_add(&histR[top32(row_hash(EMPTY32), W.logR)], parts);
+        lds_add(&histC[top32(col_hash(EMPTY32), W.logC)], parts);
       }
     };
     auto emit = [&]() {
@@ -471,7 +565,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_links(nsgc_dev_plan* P, uint32_t
       NSGC_GLOBAL u64* er = gptr(P->emit_row) + W.ws + base;
       NSGC_GLOBAL u64* ec = gptr(P->emit_col) + W.ws + base;
       const uint32_t n = misc[5];
-      for (uint32_t i0 = 0; i0 < n; i0 += U * NSGC_BLOCK) {
+      for_rounds<LINK_MAXU>(n, [&](uint32_t i0, auto uc) {
+        constexpr int U = decltype(uc)::value;
         u64 key[U];
         uint32_t cnt[U], ar[U], ac[U];
         bool ok[U];
@@ -486,22 +581,149 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_links(nsgc_dev_plan* P, uint32_t
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (ok[u]) {
-            ar[u] = lds_add(&histR[top32(row_hash(uint32_t(key[u] >> 32)), W.logR)], 1);
-            ac[u] = lds_add(&histC[top32(col_hash(uint32_t(key[u])), W.logC)], 1);
+            const uint32_t parts = entry_parts(cnt[u], 1);
+            ar[u] = lds_add(&histR[top32(row_hash(uint32_t(key[u] >> 32)), W.logR)], parts);
+            ac[u] = lds_add(&histC[top32(col_hash(uint32_t(key[u])), W.logC)], parts);
           }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (ok[u]) {
-            er[ar[u]] = (key[u] & 0xFFFFFFFF00000000ull) | cnt[u];
-            ec[ac[u]] = (key[u] << 32) | cnt[u];
+            const uint32_t parts = entry_parts(cnt[u], 1);
+            write_entry(er, ar[u], uint32_t(key[u] >> 32), cnt[u], 1, parts);
+            write_entry(ec, ac[u], uint32_t(key[u]), cnt[u], 1, parts);
           }
         }
-      }
+      });
       if (threadIdx.x == 0 && misc[1]) {
         const uint32_t c = misc[1];
-        er[lds_add(&histR[top32(row_hash(EMPTY32), W.logR)], 1)] = (u64(EMPTY32) << 32) | c;
-        ec[lds_add(&histC[top32(col_hash(EMPTY32), W.logC)], 1)] = (u64(EMPTY32) << 32) | c;
+        const uint32_t parts = entry_parts(c, 1);
+        write_entry(er, lds_add(&histR[top32(row_hash(EMPTY32), W.logR)], parts), EMPTY32, c, 1,
+                    parts);
+        write_entry(ec, lds_add(&histC[top32(col_hash(EMPTY32), W.logC)], parts), EMPTY32, c, 1,
+                    parts);
+      }
+      __syncthreads();
+    };
+
+    // Single-sweep emission with combining.  The bucket's links move to
+    // registers (at most LK per thread), the table is emptied, and its region
+    // is reused as an id table: ik = id (EMPTY32 when free), ip = complement
+    // of the packets (all-ones is 0, so the emptied link table is already an
+    // empty id table), il = links.  Each distinct id of the bucket is emitted
+    // once with its packets and links; the id EMPTY32 (the table's empty
+    // marker) is emitted per link.  If an insert gives up, the pass falls back
+    // to emitting every link on its own (links = 1), which phase C sums the
+    // same way; nothing has been emitted by then.  The touched slots are reset
+    // afterwards, which leaves the region an empty link table again.
+    auto combine_emit = [&](bool rows, const u64 (&lkey)[LK], const uint32_t (&lcnt)[LK],
+                            uint32_t nl, uint32_t spc) {
+      uint32_t* ik = reinterpret_cast<uint32_t*>(tk);
+      uint32_t* ip = ik + S;
+      uint32_t* il = tc;
+      uint32_t* io = occ;
+      uint32_t* hist = rows ? histR : histC;
+      const uint32_t K = rows ? R : C;
+      const uint32_t logK = rows ? W.logR : W.logC;
+      auto ident = [&](u64 key) { return rows ? uint32_t(key >> 32) : uint32_t(key); };
+      auto bucket = [&](uint32_t x) { return top32(rows ? row_hash(x) : col_hash(x), logK); };
+      for (uint32_t i = threadIdx.x; i <= K; i += NSGC_BLOCK) hist[i] = 0;
+      if (threadIdx.x < 2) misc[2 + threadIdx.x] = 0;   // [2] distinct ids, [3] gave up
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < LK; c += 4) {
+        uint32_t id[4], h[4], pk[4], ln[4];
+        bool ok[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          id[k] = ident(lkey[c + k]);
+          h[k] = rows ? row_hash(id[k]) : col_hash(id[k]);
+          pk[k] = lcnt[c + k];
+          ln[k] = 1;
+          ok[k] = threadIdx.x + (c + k) * NSGC_BLOCK < nl && id[k] != EMPTY32;
+          // combine the lanes holding the first valid lane's id (heavy ids)
+          const u64 vm = __ballot(ok[k]);
+          if (vm) {
+            const int first = __ffsll(static_cast<unsigned long long>(vm)) - 1;
+            const uint32_t id0 = readlane(id[k], first);
+            const bool same = ok[k] && id[k] == id0;
+            const uint32_t nsame = __popcll(__ballot(same));
+            if (nsame > 1) {
+              const uint32_t tot = wave_sum(same ? pk[k] : 0u);
+              if (same) {
+                if (int(lane_id()) == first) { pk[k] = tot; ln[k] = nsame; }
+                else ok[k] = false;
+              }
+            }
+          }
+        }
+        int slot[4];
+        bool fresh[4];
+        if (!cas_insert<4>(ik, S - 1, id, h, ok, slot, fresh, P->combine_probes))
+          lds_store(&misc[3], 1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (slot[k] >= 0) {
+            lds_sub(&ip[slot[k]], pk[k]);
+            lds_add(&il[slot[k]], ln[k]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t at = wave_append(&misc[2], fresh[k]);
+          if (fresh[k]) io[at] = uint32_t(slot[k]);
+        }
+      }
+      __syncthreads();
+      const uint32_t nd = misc[2];
+      const bool combined = misc[3] == 0;
+      // entries emitted per link: every link (fallback) or those of id EMPTY32
+      auto per_link = [&](int k) {
+        return threadIdx.x + k * NSGC_BLOCK < nl && (!combined || ident(lkey[k]) == EMPTY32);
+      };
+      if (combined) {
+        for (uint32_t i = threadIdx.x; i < nd; i += NSGC_BLOCK) {
+          const uint32_t s = io[i];
+          lds_add(&hist[bucket(ik[s])], entry_parts(~ip[s], il[s]));
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < LK; ++k)
+        if (per_link(k)) lds_add(&hist[bucket(ident(lkey[k]))], entry_parts(lcnt[k], 1));
+      if (threadIdx.x == 0 && spc) lds_add(&hist[bucket(EMPTY32)], entry_parts(spc, 1));
+      __syncthreads();
+      block_exclusive_scan(hist, K, st.red);
+      const u64 rbase = rows ? B : B + u64(R + 1) * B;
+      for (uint32_t i = threadIdx.x; i <= K; i += NSGC_BLOCK) rec[rbase + u64(i) * B + b] = hist[i];
+      __syncthreads();
+      const uint32_t base = misc[4];
+      NSGC_GLOBAL u64* e = gptr(rows ? P->emit_row : P->emit_col) + W.ws + base;
+      if (combined) {
+        for (uint32_t i = threadIdx.x; i < nd; i += NSGC_BLOCK) {
+          const uint32_t s = io[i];
+          const uint32_t x = ik[s], pk = ~ip[s], ln = il[s];
+          const uint32_t parts = entry_parts(pk, ln);
+          write_entry(e, lds_add(&hist[bucket(x)], parts), x, pk, ln, parts);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < LK; ++k) {
+        if (per_link(k)) {
+          const uint32_t x = ident(lkey[k]);
+          const uint32_t parts = entry_parts(lcnt[k], 1);
+          write_entry(e, lds_add(&hist[bucket(x)], parts), x, lcnt[k], 1, parts);
+        }
+      }
+      if (threadIdx.x == 0 && spc) {
+        const uint32_t parts = entry_parts(spc, 1);
+        write_entry(e, lds_add(&hist[bucket(EMPTY32)], parts), EMPTY32, spc, 1, parts);
+      }
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < nd; i += NSGC_BLOCK) {
+        const uint32_t s = io[i];
+        ik[s] = EMPTY32;
+        ip[s] = EMPTY32;
+        il[s] = 0;
       }
       __syncthreads();
     };
@@ -523,42 +745,68 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_links(nsgc_dev_plan* P, uint32_t
       for (uint32_t i = threadIdx.x; i < R; i += NSGC_BLOCK) histR[i] = 0;
       for (uint32_t i = threadIdx.x; i < C; i += NSGC_BLOCK) histC[i] = 0;
       bool failed = false;
-      // pass 1: statistics and link counts (one sweep also emits directly)
-      for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
-        build(logS, sw);
-        if (misc[0]) { failed = true; reset(); break; }
-        const uint32_t n = misc[5];
-        for (uint32_t i = threadIdx.x; i < n; i += NSGC_BLOCK) {
-          const uint32_t c = tc[occ[i]];
-          sum += c;
-          mx = max(mx, c);
-        }
-        if (threadIdx.x == 0) {
-          links += n;
-          if (misc[1]) {
-            ++links;
-            sum += misc[1];
-            mx = max(mx, misc[1]);
-          }
-        }
-        count();
-        __syncthreads();
-        if (logS == 0) {
+      // pass 0: statistics and link counts (a single sweep also emits);
+      // pass 1 (sweeps only): emission at the counted positions.  One call
+      // site of each step keeps the kernel's code small.
+      const uint32_t passes = logS ? 2u : 1u;
+#pragma nounroll
+      for (uint32_t pass = 0; pass < passes && !failed; ++pass) {
+        if (pass == 1) {
           publish();
           __syncthreads();
-          emit();
         }
-        reset();
-      }
-      // pass 2 (sweeps only): emit at the counted positions
-      if (!failed && logS > 0) {
-        publish();
-        __syncthreads();
+#pragma nounroll
         for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
           build(logS, sw);
           if (misc[0]) { failed = true; reset(); break; }
-          emit();
-          reset();
+          if (pass == 1) {
+            emit();
+            reset();
+            continue;
+          }
+          const uint32_t n = misc[5];
+          for (uint32_t i = threadIdx.x; i < n; i += NSGC_BLOCK) {
+            const uint32_t c = tc[occ[i]];
+            sum += c;
+            mx = max(mx, c);
+          }
+          if (threadIdx.x == 0) {
+            links += n;
+            if (misc[1]) {
+              ++links;
+              sum += misc[1];
+              mx = max(mx, misc[1]);
+            }
+          }
+          if (logS == 0 && !COMBINE) {
+            // the only sweep, emitted per link
+            count();
+            __syncthreads();
+            publish();
+            __syncthreads();
+            emit();
+            reset();
+          } else if (COMBINE && logS == 0) {
+            // the only sweep: combine per source and per destination, emit
+            u64 lkey[LK];
+            uint32_t lcnt[LK];
+#pragma unroll
+            for (int k = 0; k < LK; ++k) {
+              const uint32_t i = threadIdx.x + k * NSGC_BLOCK;
+              const uint32_t s = i < n ? occ[i] : 0u;
+              lkey[k] = i < n ? tk[s] : 0ull;
+              lcnt[k] = i < n ? tc[s] : 0u;
+            }
+            const uint32_t spc = misc[1];
+            __syncthreads();
+            reset();
+            combine_emit(true, lkey, lcnt, n, spc);
+            combine_emit(false, lkey, lcnt, n, spc);
+          } else {
+            count();
+            __syncthreads();
+            reset();
+          }
         }
       }
       if (!failed) break;
@@ -588,11 +836,11 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_links(nsgc_dev_plan* P, uint32_t
 // ---------------------------------------------------------------------------
 // Phase C: aggregation of one row bucket (or column bucket).
 //
-// Gathers the bucket's (id, packets) entries -- one per link -- from every
-// link bucket into an LDS table id -> (packets, links): this yields r(s) and
-// f(s) (or c(d) and g(d)) for every id of the bucket, hence its share of
-// stats 3-5 (or 6-8).  Entries that repeat the first valid lane's id are
-// pre-combined with one ballot and one DPP sum.  As in phase B the occupied
+// Gathers the bucket's (id, packets, links) entries -- at most one per id and
+// link bucket -- from every link bucket into an LDS table id -> (packets,
+// links): summing them yields r(s) and f(s) (or c(d) and g(d)) for every id
+// of the bucket, hence its share of stats 3-5 (or 6-8).  Entries that repeat
+// the first valid lane's id are pre-combined with one ballot and DPP sums.  As in phase B the occupied
 // slots are listed, and overflow splits the bucket into sweeps by id-hash
 // bits.
 // ---------------------------------------------------------------------------
@@ -602,7 +850,7 @@ size_t lds_rc_bytes(uint32_t slots_log2) {
   return align16(S * 4) * 4 + align16(NSGC_MAX_SEG * 8) + align16((NSGC_MAX_SEG + 1) * 4) + 256;
 }
 
-__global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol(nsgc_dev_plan* P) {
+__global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_rowcol(nsgc_dev_plan* P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t S = 1u << P->rc_slots_log2;
   unsigned char* p = smem;
@@ -662,15 +910,16 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol(nsgc_dev_plan* P) {
     auto build = [&](uint32_t logS, uint32_t sw) {
       if (threadIdx.x < 4) misc[threadIdx.x] = 0;
       __syncthreads();
-      gather_segments(B, st, seg, [&](const u64 (&pos)[U], const bool (&okin)[U]) {
+      gather_segments<RC_MAXU>(B, st, seg, [&](const auto& pos, const auto& okin) {
+        constexpr int U = array_len<decltype(pos)>();
         uint32_t id[U], h[U], pk[U], ln[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const u64 e = okin[u] ? em[pos[u]] : 0ull;
           id[u] = uint32_t(e >> 32);
-          pk[u] = uint32_t(e);
-          ln[u] = 1;
+          pk[u] = uint32_t(e) & ENT_PMAX;
+          ln[u] = uint32_t(e) >> NSGC_ENT_PACKET_BITS;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -678,7 +927,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol(nsgc_dev_plan* P) {
           ok[u] = okin[u] && !(logS && next32(h[u], logK, logS) != sw);
           if (ok[u] && id[u] == EMPTY32) {
             lds_add(&misc[2], pk[u]);
-            lds_add(&misc[3], 1);
+            lds_add(&misc[3], ln[u]);
             ok[u] = false;
           }
           // combine the lanes holding the first valid lane's id
@@ -690,8 +939,9 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol(nsgc_dev_plan* P) {
             const uint32_t nsame = __popcll(__ballot(same));
             if (nsame > 1) {
               const uint32_t tot = wave_sum(same ? pk[u] : 0u);
+              const uint32_t lns = wave_sum(same ? ln[u] : 0u);
               if (same) {
-                if (int(lane_id()) == first) { pk[u] = tot; ln[u] = nsame; }
+                if (int(lane_id()) == first) { pk[u] = tot; ln[u] = lns; }
                 else ok[u] = false;
               }
             }
@@ -707,7 +957,11 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol(nsgc_dev_plan* P) {
             lds_add(&ta[slot[u]], pk[u]);
             lds_add(&tb[slot[u]], ln[u]);
           }
-          if (fresh[u]) occ[lds_add(&misc[5], 1)] = uint32_t(slot[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t at = wave_append(&misc[5], fresh[u]);
+          if (fresh[u]) occ[at] = uint32_t(slot[u]);
         }
       });
     };
@@ -776,10 +1030,14 @@ hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t
   return hipGetLastError();
 }
 
-hipError_t launch_links(const nsgc_dev_plan* P, uint32_t max_buckets, uint32_t grid, size_t lds,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_links, dim3(grid), dim3(NSGC_BLOCK), lds, s, const_cast<nsgc_dev_plan*>(P),
-                     max_buckets);
+hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_buckets, uint32_t grid,
+                        size_t lds, hipStream_t s) {
+  if (combine)
+    hipLaunchKernelGGL(k_links<true>, dim3(grid), dim3(NSGC_BLOCK), lds, s,
+                       const_cast<nsgc_dev_plan*>(P), max_buckets);
+  else
+    hipLaunchKernelGGL(k_links<false>, dim3(grid), dim3(NSGC_BLOCK), lds, s,
+                       const_cast<nsgc_dev_plan*>(P), max_buckets);
   return hipGetLastError();
 }
 
@@ -788,10 +1046,32 @@ hipError_t launch_rowcol(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipS
   return hipGetLastError();
 }
 
+hipError_t resident_blocks(int which, uint32_t tile_log2, size_t lds, int* blocks) {
+  const void* f = nullptr;
+  switch (which) {
+    case 0: f = reinterpret_cast<const void*>(&k_small); break;
+    case 1:
+      switch (tile_log2) {
+        case 11: f = reinterpret_cast<const void*>(&k_partition<4>); break;
+        case 12: f = reinterpret_cast<const void*>(&k_partition<8>); break;
+        case 13: f = reinterpret_cast<const void*>(&k_partition<16>); break;
+        case 14: f = reinterpret_cast<const void*>(&k_partition<32>); break;
+        default: return hipErrorInvalidValue;
+      }
+      break;
+    case 2: f = reinterpret_cast<const void*>(&k_links<false>); break;
+    case 4: f = reinterpret_cast<const void*>(&k_links<true>); break;
+    case 3: f = reinterpret_cast<const void*>(&k_rowcol); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, NSGC_BLOCK, lds);
+}
+
 hipError_t allow_large_lds(size_t bytes) {
   const int b = int(bytes);
   const void* fns[] = {
-      reinterpret_cast<const void*>(&k_small),         reinterpret_cast<const void*>(&k_links),
+      reinterpret_cast<const void*>(&k_small),         reinterpret_cast<const void*>(&k_links<false>),
+      reinterpret_cast<const void*>(&k_links<true>),
       reinterpret_cast<const void*>(&k_rowcol),        reinterpret_cast<const void*>(&k_partition<4>),
       reinterpret_cast<const void*>(&k_partition<8>),  reinterpret_cast<const void*>(&k_partition<16>),
       reinterpret_cast<const void*>(&k_partition<32>)};

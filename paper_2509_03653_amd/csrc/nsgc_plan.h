@@ -15,9 +15,11 @@
 //     B  link aggregation: one item per link bucket gathers its segments from
 //        every tile into an LDS hash table (key -> packet count).  This gives
 //        A's non-zeros: sum, count and max per bucket (stats 0-2).  The
-//        de-duplicated links are then emitted twice, as (src, packets) grouped
-//        by row bucket and as (dst, packets) grouped by column bucket, into
-//        the bucket's own emission region (as many slots as it has packets).
+//        bucket's links are then combined per source and per destination
+//        and emitted as (src, packets, links) grouped by row bucket and
+//        (dst, packets, links) grouped by column bucket, into the bucket's own
+//        emission region (as many slots as it has packets).  A source with
+//        many links thus leaves one entry per link bucket, not one per link.
 //     C  row / column aggregation: one item per row bucket and per column
 //        bucket gathers its runs from every link bucket into an LDS table
 //        id -> (packets, links), giving stats 3-5 and 6-8.
@@ -31,6 +33,15 @@
 #define NSGC_BLOCK 512          // threads per workgroup in every kernel
 #define NSGC_MAX_SEG 512        // segments staged in LDS at a time (phases B, C)
 #define NSGC_UNROLL 8           // elements per thread in flight in the B/C gathers
+
+// A phase-B emission entry packs an id with the links and packets it stands
+// for: id << 32 | links << 19 | packets.  A link bucket holds at most 4096
+// links, so the link field never overflows; a triple with more packets than
+// the packet field holds is emitted as several entries that sum to it (phase C
+// adds them up).  Since links <= packets no triple needs more entries than it
+// has packets, so an emission region of one slot per packet suffices.
+#define NSGC_ENT_PACKET_BITS 19
+#define NSGC_ENT_LINK_BITS 13
 
 struct nsgc_small_desc {        // 16 bytes
   int64_t in_begin;             // index of the window's first packet
@@ -69,8 +80,8 @@ struct nsgc_dev_plan {          // header of the device plan buffer
   const uint32_t* dst;
   unsigned long long* out;      // 9 x u64 per window
   unsigned long long* keys;     // partitioned packed keys
-  unsigned long long* emit_row; // one entry per link: (src << 32 | packets)
-  unsigned long long* emit_col; // one entry per link: (dst << 32 | packets)
+  unsigned long long* emit_row; // row entries (src, links, packets), packed below
+  unsigned long long* emit_col; // column entries (dst, links, packets)
   uint32_t* tilemeta;
   uint32_t* lbmeta;
   uint32_t* counters;
@@ -87,7 +98,8 @@ struct nsgc_dev_plan {          // header of the device plan buffer
   uint32_t rc_slots_log2;
   uint32_t small_slots_log2;
   uint32_t max_sweeps_log2;     // overflow sweeps allowed before a bucket is abandoned
-  uint32_t pad[2];
+  uint32_t combine_probes;      // 0: per-link emission; else probe limit of the combining table
+  uint32_t pad;
   // Work-queue counters of the small, B and C kernels (workgroups take items
   // in order with an atomic increment).  Uploaded as zero with every plan.
   uint32_t queue[4];

@@ -27,6 +27,7 @@ void default_tune(nsgc_tune* t) {
   t->blocks_per_cu = 2;
   t->max_buckets_log2 = 10;
   t->max_sweeps_log2 = 24;
+  t->combine_probes = 0;
   for (int k = 0; k <= 32; ++k) {
     t->cls[k].link_target = 2048;
     t->cls[k].row_target = 4096;
@@ -42,6 +43,7 @@ int check_tune(const nsgc_tune& t) {
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16) return NSGC_ERR_INVALID_ARG;
   if (t.max_buckets_log2 < 0 || t.max_buckets_log2 > 12) return NSGC_ERR_INVALID_ARG;
   if (t.max_sweeps_log2 < 0 || t.max_sweeps_log2 > 24) return NSGC_ERR_INVALID_ARG;
+  if (t.combine_probes < 0 || t.combine_probes > 64) return NSGC_ERR_INVALID_ARG;
   for (int k = 0; k <= 32; ++k) {
     const nsgc_tune_class& c = t.cls[k];
     if (c.link_target < 64 || c.row_target < 64 || c.col_target < 64) return NSGC_ERR_INVALID_ARG;
@@ -72,6 +74,7 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
   p->link_slots_log2 = uint32_t(tune.link_slots_log2);
   p->rc_slots_log2 = uint32_t(tune.rc_slots_log2);
   p->max_sweeps_log2 = uint32_t(tune.max_sweeps_log2);
+  p->combine_probes = uint32_t(tune.combine_probes);
   p->small_slots_log2 = uint32_t(std::max(ceil_log2(uint64_t(std::max(tune.small_max, 1)) * 2), 6));
 
   const uint64_t tile = uint64_t(1) << tune.tile_log2;
@@ -192,6 +195,7 @@ void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const ui
   h.rc_slots_log2 = rc_slots_log2;
   h.small_slots_log2 = small_slots_log2;
   h.max_sweeps_log2 = max_sweeps_log2;
+  h.combine_probes = combine_probes;
   std::memcpy(base, &h, sizeof h);
   if (!small.empty()) std::memcpy(base + o.small, small.data(), small.size() * sizeof(nsgc_small_desc));
   if (!win.empty()) std::memcpy(base + o.win, win.data(), win.size() * sizeof(nsgc_win_desc));

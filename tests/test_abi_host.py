@@ -78,7 +78,8 @@ def test_tune_roundtrip_and_validation():
     assert d["max_sweeps_log2"] == 24
     for k, v in (("tile_log2", 9), ("tile_log2", 15), ("link_slots_log2", 13),
                  ("rc_slots_log2", 14), ("small_max", 2049), ("blocks_per_cu", 0),
-                 ("max_buckets_log2", 13), ("max_sweeps_log2", 25), ("max_sweeps_log2", -1)):
+                 ("max_buckets_log2", 13), ("max_sweeps_log2", 25), ("max_sweeps_log2", -1),
+                 ("combine_probes", -1), ("combine_probes", 65)):
         with pytest.raises(nsgc.NsgcError):
             nsgc.set_tune(nsgc.Tune.from_dict(dict(d, **{k: v})))
         assert nsgc.get_tune().to_dict() == d, k

@@ -138,6 +138,11 @@ TUNES = {
     "one_bucket": dict(max_buckets_log2=0),
     "many_buckets": dict(cls=[[64, 64, 64]] * 33, max_buckets_log2=12),
     "big_tables": dict(link_slots_log2=12, rc_slots_log2=13, blocks_per_cu=1),
+    # per-id combining in phase B, and its fallback (gives up almost always)
+    "combine": dict(combine_probes=64),
+    "combine_fallback": dict(combine_probes=1),
+    "combine_fallback_tight": dict(combine_probes=2, link_slots_log2=10,
+                                   cls=[[512, 4096, 4096]] * 33),
 }
 
 
@@ -206,6 +211,30 @@ def test_stream_argument_and_out_reuse():
     nsgc.window_stats(s, d, wl.offsets, out=out, stream=st)
     st.synchronize()
     assert_same(out.cpu().numpy().view(np.uint64), want, "side stream")
+
+
+def test_heavy_links_split_entries():
+    # links with more packets than an emission entry's packet field holds
+    # (2^19 - 1) are emitted as several entries; every path must sum them
+    n = 1_300_000
+    rng = np.random.default_rng(31)
+    src = rng.integers(0, 50, n).astype(np.uint32)
+    dst = rng.integers(0, 50, n).astype(np.uint32)
+    src[: 600_000], dst[: 600_000] = 1, 2          # one link of 600K packets
+    src[600_000: 1_200_000] = 1                    # source 1: 1.2M packets
+    dst[600_000: 1_200_000] = 3
+    perm = rng.permutation(n)
+    src, dst = src[perm], dst[perm]
+    off = synth.offsets_from_sizes([n, 1000, n // 2])
+    s2 = np.concatenate([src, src[:1000], src[: n // 2]])
+    d2 = np.concatenate([dst, dst[:1000], dst[: n // 2]])
+    check(s2, d2, off, "heavy links", forms=("batched", "plain"))
+    for extra in (dict(max_buckets_log2=0), dict(combine_probes=1), dict(combine_probes=64),
+                  dict(link_slots_log2=10, max_buckets_log2=0)):   # overflow sweeps
+        base = nsgc.default_tune().to_dict()
+        base.update(extra)
+        nsgc.set_tune(nsgc.Tune.from_dict(base))
+        check(s2, d2, off, f"heavy links {extra}")
 
 
 def test_abandoned_bucket_is_reported_not_hung():
