@@ -12,7 +12,9 @@ HBM, not the cache.
 
 Prints ONE JSON line.  Also reports the plain one-window-per-launch form, the
 direct (uncaptured) batched form, per-kernel HIP-event times with the roofline
-of the dominant kernel, and the CPU oracle as a baseline on a bounded sample.
+of the dominant kernel, the CPU oracle as a baseline on a bounded sample, and
+a serving leg: continuous batching of Poisson-arriving windows (log-uniform
+2^12..2^22 packets) with p50/p99 latency at three offered rates.
 
 Extra modes:
   --profile-steps N   only run N batched graph steps plus one calibration copy
@@ -163,6 +165,67 @@ def summarize_pmc(fetch_dir, write_dir):
     print(json.dumps(result))
 
 
+def serving_leg(args, nsgc, torch):
+    """Continuous-batching server over Poisson arrivals (windows log-uniform in
+    [2^12, 2^22] packets, Zipf(1.2) over 2^24 addresses): the closed-loop
+    saturation rate, then open-loop runs at 0.5, 0.8 and 1.0 of it.  Requests
+    are served from a pool of generated windows in pinned host memory;
+    latency runs from arrival to statistics on the host."""
+    import synth
+    from paper_2509_03653_amd import serving as sv
+
+    pool_n = args.serving_pool
+    wl = synth.serving_stream(seed=args.seed, num_windows=pool_n)
+    src, dst = wl.generate()
+    off = wl.offsets
+    src_pin = torch.from_numpy(src.view(np.int32)).pin_memory()
+    dst_pin = torch.from_numpy(dst.view(np.int32)).pin_memory()
+    # reference: the pool windows in one batched call
+    ref = nsgc.window_stats(src_pin.cuda(), dst_pin.cuda(), off)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy().view(np.uint64)
+
+    cap = 1 << 27
+    ex = sv.GpuExecutor(cap, max_batch_windows=1024, streams=2)
+    n_total = args.serving_warmup + args.serving_windows
+
+    def requests():
+        out = []
+        for i in range(n_total):
+            k = i % pool_n
+            a, b = int(off[k]), int(off[k + 1])
+            r = sv.Request(i, src_pin[a:b], dst_pin[a:b])
+            r.pool = k
+            out.append(r)
+        return out
+
+    def serve(times):
+        srv = sv.Server(ex, cap, inflight=2, max_batch_windows=1024)
+        res = srv.run(requests(), arrival_times=times, warmup=args.serving_warmup, timeout_s=300)
+        for r in res.requests:
+            if not np.array_equal(r.stats, ref[r.pool]):
+                raise SystemExit(f"served window {r.rid} differs from the same window alone")
+        return res.summary()
+
+    serve(None)                                   # warm-up of streams and workspaces
+    sat = serve(None)
+    lam = sat["windows_per_s"]
+    rates = []
+    for frac in (0.5, 0.8, 1.0):
+        s = serve(sv.poisson_arrivals(n_total, frac * lam, seed=args.seed + int(frac * 10)))
+        rates.append({"fraction_of_saturation": frac, "offered_windows_per_s": frac * lam,
+                      "windows_per_s": s["windows_per_s"], "packets_per_s": s["packets_per_s"],
+                      "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"],
+                      "mean_batch_windows": s["mean_batch_windows"]})
+    return {"workload": "Poisson arrivals, windows log-uniform in [2^12, 2^22] packets, "
+                        "Zipf(1.2) over 2^24 addresses",
+            "pool_windows": pool_n, "windows_per_rate": args.serving_windows,
+            "warmup_windows": args.serving_warmup, "arena_packets": cap,
+            "saturation": {"windows_per_s": lam, "packets_per_s": sat["packets_per_s"],
+                           "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"]},
+            "rates": rates, "exact": True}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +234,10 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle wall time for the CPU baseline (0 disables)")
+    ap.add_argument("--serving-windows", type=int, default=2000,
+                    help="measured windows per offered rate of the serving leg (0 disables)")
+    ap.add_argument("--serving-warmup", type=int, default=200)
+    ap.add_argument("--serving-pool", type=int, default=256)
     ap.add_argument("--profile-steps", type=int, default=0)
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
@@ -251,6 +318,10 @@ def main():
         if tr.get("kernel_source") == kernel_source_hash() and dominant in tr.get("kernels", {}):
             traffic = tr["kernels"][dominant]["hbm_bytes"]
 
+    serving = None
+    if args.serving_windows > 0:
+        serving = serving_leg(args, nsgc, torch)
+
     cpu = None
     if args.cpu_budget > 0:
         cpu = cpu_baseline(src, dst, off, args.cpu_budget)
@@ -283,6 +354,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     graph.close()
     print(json.dumps(line), flush=True)
