@@ -78,6 +78,8 @@ constexpr u64 NSGC_INVALID_BIT = 1ull << 63;
 // VGPRs, i.e. two 512-thread workgroups per compute unit.
 constexpr int LINK_MAXU = 4;
 constexpr int RC_MAXU = 4;
+// Phase C stages fewer segments at a time so that three workgroups fit a CU.
+constexpr uint32_t RC_MAXSEG = 256;
 // Links a thread holds while phase B combines them per source and
 // destination: the link table has at most LK * NSGC_BLOCK slots.
 constexpr int LK = 8;
@@ -345,23 +347,23 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* _
 
 // ---------------------------------------------------------------------------
 // Shared machinery of phases B and C: visit the elements of up to
-// NSGC_MAX_SEG segments at a time, up to U per thread per round.  `seg(i,
+// MAXSEG segments at a time, up to U per thread per round.  `seg(i,
 // base, len)` describes segment i; `fn(pos, ok)` receives arrays of the
 // round's flat positions (pos[u] valid when ok[u]; the array length is the
 // round's unroll) with the whole wavefront active.
 // ---------------------------------------------------------------------------
 
 struct SegStage {
-  u64* base;       // [NSGC_MAX_SEG]
-  uint32_t* off;   // [NSGC_MAX_SEG + 1]
+  u64* base;       // [MAXSEG]
+  uint32_t* off;   // [MAXSEG + 1]
   uint32_t* red;   // [2 * WAVES]
 };
 
-template <int MAXU, class SegFn, class BatchFn>
+template <int MAXU, uint32_t MAXSEG, class SegFn, class BatchFn>
 __device__ __forceinline__ void gather_segments(uint32_t nseg, const SegStage& st, SegFn seg,
                                                 BatchFn fn) {
-  for (uint32_t c0 = 0; c0 < nseg; c0 += NSGC_MAX_SEG) {
-    const uint32_t cn = min(uint32_t(NSGC_MAX_SEG), nseg - c0);
+  for (uint32_t c0 = 0; c0 < nseg; c0 += MAXSEG) {
+    const uint32_t cn = min(MAXSEG, nseg - c0);
     for (uint32_t i = threadIdx.x; i < cn; i += NSGC_BLOCK) {
       u64 b;
       uint32_t l;
@@ -497,7 +499,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
     auto build = [&](uint32_t logS, uint32_t sw) {
       if (threadIdx.x < 2) misc[threadIdx.x] = 0;
       __syncthreads();
-      gather_segments<LINK_MAXU>(nt, st, seg, [&](const auto& pos, const auto& okin) {
+      gather_segments<LINK_MAXU, NSGC_MAX_SEG>(nt, st, seg, [&](const auto& pos, const auto& okin) {
         constexpr int U = array_len<decltype(pos)>();
         u64 key[U];
         uint32_t h[U], add[U];
@@ -847,22 +849,21 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 
 size_t lds_rc_bytes(uint32_t slots_log2) {
   const size_t S = size_t(1) << slots_log2;
-  return align16(S * 4) * 4 + align16(NSGC_MAX_SEG * 8) + align16((NSGC_MAX_SEG + 1) * 4) + 256;
+  return align16(S * 4) * 3 + align16(RC_MAXSEG * 8) + align16((RC_MAXSEG + 1) * 4) + 256;
 }
 
-__global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_rowcol(nsgc_dev_plan* P) {
+__global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_rowcol(nsgc_dev_plan* P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t S = 1u << P->rc_slots_log2;
   unsigned char* p = smem;
   uint32_t* tk = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
   uint32_t* ta = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
   uint32_t* tb = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
-  uint32_t* occ = reinterpret_cast<uint32_t*>(p);      p += align16(S * 4);
   SegStage st;
-  st.base = reinterpret_cast<u64*>(p);                 p += align16(NSGC_MAX_SEG * 8);
-  st.off = reinterpret_cast<uint32_t*>(p);             p += align16((NSGC_MAX_SEG + 1) * 4);
+  st.base = reinterpret_cast<u64*>(p);                 p += align16(RC_MAXSEG * 8);
+  st.off = reinterpret_cast<uint32_t*>(p);             p += align16((RC_MAXSEG + 1) * 4);
   uint32_t* misc = reinterpret_cast<uint32_t*>(p);     // [0] fail flag, [2,3] special id,
-                                                       // [5] occupied slots, [7] queue slot
+                                                       // [7] queue slot
   st.red = misc + 8;
 
   for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
@@ -870,7 +871,6 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
     ta[i] = 0;
     tb[i] = 0;
   }
-  if (threadIdx.x == 0) misc[5] = 0;
 
   const uint32_t items = P->itemsC;
   ItemQueue q{gptr(&P->queue[2]), misc + 7, 0};
@@ -894,23 +894,42 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
       len = s1 - s0;
     };
 
-    auto reset = [&]() {
-      const uint32_t n = misc[5];
-      for (uint32_t i = threadIdx.x; i < n; i += NSGC_BLOCK) {
-        const uint32_t s = occ[i];
-        tk[s] = EMPTY32;
-        ta[s] = 0;
-        tb[s] = 0;
+    // One pass over every slot (16-byte LDS accesses): fold the occupied
+    // slots into the statistics when `take`, and empty the table.  Tables of
+    // <= 8192 slots make this a few accesses per thread, cheaper than keeping
+    // a list of occupied slots in the inserts.
+    uint32_t n = 0, mp = 0, ml = 0;
+    auto harvest = [&](bool take) {
+      const v4u32 empty4 = {EMPTY32, EMPTY32, EMPTY32, EMPTY32};
+      const v4u32 zero4 = {0u, 0u, 0u, 0u};
+      for (uint32_t i = threadIdx.x * 4; i < S; i += NSGC_BLOCK * 4) {
+        const v4u32 k4 = *reinterpret_cast<const v4u32*>(tk + i);
+        if (take) {
+          const v4u32 a4 = *reinterpret_cast<const v4u32*>(ta + i);
+          const v4u32 b4 = *reinterpret_cast<const v4u32*>(tb + i);
+          const uint32_t ks[4] = {k4.x, k4.y, k4.z, k4.w};
+          const uint32_t as[4] = {a4.x, a4.y, a4.z, a4.w};
+          const uint32_t bs[4] = {b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (ks[j] != EMPTY32) {
+              ++n;
+              mp = max(mp, as[j]);
+              ml = max(ml, bs[j]);
+            }
+          }
+        }
+        *reinterpret_cast<v4u32*>(tk + i) = empty4;
+        *reinterpret_cast<v4u32*>(ta + i) = zero4;
+        *reinterpret_cast<v4u32*>(tb + i) = zero4;
       }
-      __syncthreads();
-      if (threadIdx.x == 0) misc[5] = 0;
       __syncthreads();
     };
 
     auto build = [&](uint32_t logS, uint32_t sw) {
       if (threadIdx.x < 4) misc[threadIdx.x] = 0;
       __syncthreads();
-      gather_segments<RC_MAXU>(B, st, seg, [&](const auto& pos, const auto& okin) {
+      gather_segments<RC_MAXU, RC_MAXSEG>(B, st, seg, [&](const auto& pos, const auto& okin) {
         constexpr int U = array_len<decltype(pos)>();
         uint32_t id[U], h[U], pk[U], ln[U];
         bool ok[U];
@@ -958,15 +977,10 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
             lds_add(&tb[slot[u]], ln[u]);
           }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const uint32_t at = wave_append(&misc[5], fresh[u]);
-          if (fresh[u]) occ[at] = uint32_t(slot[u]);
-        }
+        (void)fresh;
       });
     };
 
-    uint32_t n = 0, mp = 0, ml = 0;
     bool abandoned = false;
     for (uint32_t logS = 0;; ++logS) {
       if (logS > P->max_sweeps_log2) { abandoned = true; break; }
@@ -974,22 +988,15 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
       bool failed = false;
       for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
         build(logS, sw);
-        if (misc[0]) { failed = true; reset(); break; }
-        const uint32_t m = misc[5];
-        for (uint32_t i = threadIdx.x; i < m; i += NSGC_BLOCK) {
-          const uint32_t s = occ[i];
-          mp = max(mp, ta[s]);
-          ml = max(ml, tb[s]);
-        }
+        if (misc[0]) { failed = true; harvest(false); break; }
+        harvest(true);
         if (threadIdx.x == 0) {
-          n += m;
           if (misc[3]) {
             ++n;
             mp = max(mp, misc[2]);
             ml = max(ml, misc[3]);
           }
         }
-        reset();
       }
       if (!failed) break;
     }

@@ -24,7 +24,7 @@ void default_tune(nsgc_tune* t) {
   t->tile_log2 = 13;
   t->link_slots_log2 = 12;
   t->rc_slots_log2 = 12;
-  t->blocks_per_cu = 2;
+  t->blocks_per_cu = 3;
   t->max_buckets_log2 = 10;
   t->max_sweeps_log2 = 24;
   t->combine_probes = 0;
