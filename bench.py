@@ -60,11 +60,36 @@ def algorithmic_bytes(num_packets: int, num_windows: int) -> int:
     return 8 * num_packets + 80 * num_windows
 
 
+WORKLOAD_TEXT = {
+    "zipf_batch": "64 windows x 2^17 packets, src Zipf(1.2) over 2^20 addresses, "
+                  "dst Zipf(1.0) over 2^24 addresses",
+    "uniform_single": "1 window x 2^17 packets, src and dst uniform over 4096 addresses",
+    "skewed_large": "128 windows x 2^23 packets, 10% from one super-source, 1% to one "
+                    "super-destination, rest Zipf(1.3) over 2^26 addresses",
+    "uneven_batch": "4096 windows, sizes log-uniform in [2^10, 2^23], Zipf(1.1) over 2^22 "
+                    "addresses",
+}
+
+
 def make_inputs(args):
     import synth
-    wl = synth.zipf_batch(seed=args.seed)
+    wl = synth.WORKLOADS[args.workload](seed=args.seed)
     src, dst = wl.generate()
     return wl, src, dst
+
+
+def sample_windows(num_windows: int):
+    return sorted({0, num_windows // 3, (2 * num_windows) // 3, num_windows - 1})
+
+
+def oracle_on(src, dst, offsets, windows, threads):
+    """The oracle on selected windows (gathered into one batch)."""
+    import oracle
+    parts = [(int(offsets[w]), int(offsets[w + 1])) for w in windows]
+    s = np.concatenate([src[a:b] for a, b in parts])
+    d = np.concatenate([dst[a:b] for a, b in parts])
+    off = np.concatenate([[0], np.cumsum([b - a for a, b in parts])]).astype(np.int64)
+    return oracle.window_stats(s, d, off, threads=threads)
 
 
 def to_device_copies(src, dst, copies):
@@ -95,23 +120,43 @@ def time_loop(fn, steps, warmup, stream):
 
 
 def cpu_baseline(src, dst, offsets, budget_s: float):
+    """The oracle on the host cores: the whole batch, repeated while within
+    budget; for batches too large for the budget, consecutive groups of
+    windows (one window per thread) until the budget is spent."""
     import oracle
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:  # pragma: no cover
         cores = os.cpu_count() or 1
-    threads = max(1, min(cores, len(offsets) - 1))
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        oracle.window_stats(src, dst, offsets, threads=threads)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 50:
+    W = len(offsets) - 1
+    n_all = int(offsets[-1] - offsets[0])
+    if n_all <= 64 << 20:
+        threads = max(1, min(cores, W))
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            oracle.window_stats(src, dst, offsets, threads=threads)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or reps >= 50:
+                break
+        return {"value": n_all * reps / el, "unit": "packets/s", "cores": threads,
+                "kind": "oracle",
+                "sample": f"the full batch ({W} windows, {n_all} packets) run {reps}x "
+                          f"({el:.1f} s wall) with one window per thread"}
+    threads = cores
+    done_w, done_p, t0 = 0, 0, time.perf_counter()
+    while done_w < W:
+        group = range(done_w, min(W, done_w + 8 * threads))   # dynamic scheduling balances
+        a, b = int(offsets[group[0]]), int(offsets[group[-1] + 1])
+        oracle.window_stats(src[a:b], dst[a:b], offsets[group[0]:group[-1] + 2] - a,
+                            threads=threads)
+        done_w, done_p = group[-1] + 1, done_p + (b - a)
+        if time.perf_counter() - t0 >= budget_s:
             break
-    n = int(offsets[-1] - offsets[0])
-    return {"value": n * reps / el, "unit": "packets/s", "cores": threads, "kind": "oracle",
-            "sample": f"the full batch ({len(offsets) - 1} windows, {n} packets) run {reps}x "
-                      f"({el:.1f} s wall) with one window per thread"}
+    el = time.perf_counter() - t0
+    return {"value": done_p / el, "unit": "packets/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {done_w} of {W} windows ({done_p} packets, {el:.1f} s wall) "
+                      f"with one window per thread"}
 
 
 def summarize_pmc(fetch_dir, write_dir):
@@ -232,6 +277,10 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--workload", default="zipf_batch", choices=sorted(WORKLOAD_TEXT),
+                    help="batch to time (the default is the headline configuration)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="search (or load from the cache) the tuning for this batch first")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle wall time for the CPU baseline (0 disables)")
     ap.add_argument("--serving-windows", type=int, default=2000,
@@ -258,15 +307,16 @@ def main():
     wl, src, dst = make_inputs(args)
     off = wl.offsets
     P, W = wl.num_packets, wl.num_windows
-    ss, dd = to_device_copies(src, dst, COPIES)
+    copies = COPIES if P * 8 * COPIES <= (4 << 30) else 1   # big batches exceed the caches anyway
+    ss, dd = to_device_copies(src, dst, copies)
     stream = torch.cuda.current_stream()
     out = torch.empty((W, 9), dtype=torch.int64, device="cuda")
     graph = nsgc.Graph(P, W)
 
     if args.profile_steps:
         for i in range(args.profile_steps):
-            graph.launch(ss[i % COPIES], dd[i % COPIES], off, out=out, stream=stream)
-            nsgc.window_stats(ss[i % COPIES], dd[i % COPIES], off, out=out, stream=stream)
+            graph.launch(ss[i % copies], dd[i % copies], off, out=out, stream=stream)
+            nsgc.window_stats(ss[i % copies], dd[i % copies], off, out=out, stream=stream)
         torch.cuda.synchronize()
         a = torch.empty(CALIB_BYTES // 4, dtype=torch.int32, device="cuda")
         b = torch.empty_like(a)
@@ -277,24 +327,30 @@ def main():
         graph.close()
         return
 
+    tuned = None
+    if args.autotune:
+        from paper_2509_03653_amd import autotune
+        tuned = autotune.tune_for(ss[0], dd[0], off, budget_s=120.0)
+        graph.close()
+        graph = nsgc.Graph(P, W)          # a graph keeps the tuning it was created with
+
     # parity gate on sampled windows before timing
-    import oracle
     graph.launch(ss[0], dd[0], off, out=out, stream=stream)
     torch.cuda.synchronize()
     got = out.cpu().numpy().view(np.uint64)
-    sample = [0, 21, 42, 63]
-    want = oracle.window_stats(src, dst, off, threads=4)
-    if not np.array_equal(got[sample], want[sample]):
+    sample = sample_windows(W)
+    want = oracle_on(src, dst, off, sample, threads=len(sample))
+    if not np.array_equal(got[sample], want):
         raise SystemExit("parity check failed before timing")
 
     def step_graph(i):
-        graph.launch(ss[i % COPIES], dd[i % COPIES], off, out=out, stream=stream)
+        graph.launch(ss[i % copies], dd[i % copies], off, out=out, stream=stream)
 
     def step_direct(i):
-        nsgc.window_stats(ss[i % COPIES], dd[i % COPIES], off, out=out, stream=stream)
+        nsgc.window_stats(ss[i % copies], dd[i % copies], off, out=out, stream=stream)
 
     def step_plain(i):
-        nsgc.window_stats_plain(ss[i % COPIES], dd[i % COPIES], off, out=out, stream=stream)
+        nsgc.window_stats_plain(ss[i % copies], dd[i % copies], off, out=out, stream=stream)
 
     ms_graph = time_loop(step_graph, args.steps, args.warmup, stream)
     ms_direct = time_loop(step_direct, args.steps, args.warmup, stream)
@@ -303,7 +359,7 @@ def main():
     # per-kernel HIP-event times on the launch stream
     phases = {k: [] for k in nsgc.PHASES}
     for i in range(args.steps):
-        _, ph = nsgc.window_stats_timed(ss[i % COPIES], dd[i % COPIES], off, out=out, stream=stream)
+        _, ph = nsgc.window_stats_timed(ss[i % copies], dd[i % copies], off, out=out, stream=stream)
         for k, v in ph.items():
             phases[k].append(v)
     phase_ms = {k: float(np.mean(v)) for k, v in phases.items()}
@@ -319,7 +375,7 @@ def main():
             traffic = tr["kernels"][dominant]["hbm_bytes"]
 
     serving = None
-    if args.serving_windows > 0:
+    if args.serving_windows > 0 and args.workload == "zipf_batch":
         serving = serving_leg(args, nsgc, torch)
 
     cpu = None
@@ -339,9 +395,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
-        "data": "synthetic (seeded Zipf traffic; inputs resident in HBM, 8 rotating copies)",
-        "config": {"workload": "64 windows x 2^17 packets, src Zipf(1.2) over 2^20 addresses, "
-                               "dst Zipf(1.0) over 2^24 addresses",
+        "data": f"synthetic (seeded traffic; inputs resident in HBM, {copies} rotating "
+                f"cop{'ies' if copies > 1 else 'y'})",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "windows": W, "packets": P, "seed": args.seed, "form": "batched, graph"},
         "batched_direct_packets_per_s": P / (ms_direct * 1e-3),
         "plain_packets_per_s": P / (ms_plain * 1e-3),
@@ -356,6 +412,9 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
     }
+    if tuned is not None:
+        line["autotune"] = {"tune": tuned["tune"], "default_ms": tuned.get("default_ms"),
+                            "tuned_ms": tuned.get("ms"), "cached": tuned.get("cached")}
     graph.close()
     print(json.dumps(line), flush=True)
 
