@@ -183,6 +183,59 @@ __device__ __forceinline__ void block_sum_max(uint32_t& sum, uint32_t& mx, uint3
   mx = tm;
 }
 
+// Sums of a and b and the max of m over the block, valid in thread 0 only
+// (one barrier).  `red` (3*WAVES words) must not be reused before the block
+// has passed another barrier.
+__device__ __forceinline__ void block_sum2_max_to0(uint32_t& a, uint32_t& b, uint32_t& m,
+                                                   uint32_t* red) {
+  const uint32_t sa = wave_sum(a), sb = wave_sum(b), sm = wave_max(m);
+  const uint32_t w = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    red[w] = sa;
+    red[WAVES + w] = sb;
+    red[2 * WAVES + w] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t ta = 0, tb = 0, tm = 0;
+#pragma unroll
+    for (int k = 0; k < WAVES; ++k) {
+      ta += red[k];
+      tb += red[WAVES + k];
+      tm = max(tm, red[2 * WAVES + k]);
+    }
+    a = ta;
+    b = tb;
+    m = tm;
+  }
+}
+
+// The sum of s and the maxima of m1 and m2 over the block, valid in thread 0
+// only (one barrier; same reuse rule for `red` as above).
+__device__ __forceinline__ void block_sum_max2_to0(uint32_t& s, uint32_t& m1, uint32_t& m2,
+                                                   uint32_t* red) {
+  const uint32_t ss = wave_sum(s), s1 = wave_max(m1), s2 = wave_max(m2);
+  const uint32_t w = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    red[w] = ss;
+    red[WAVES + w] = s1;
+    red[2 * WAVES + w] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t ts = 0, t1 = 0, t2 = 0;
+#pragma unroll
+    for (int k = 0; k < WAVES; ++k) {
+      ts += red[k];
+      t1 = max(t1, red[WAVES + k]);
+      t2 = max(t2, red[2 * WAVES + k]);
+    }
+    s = ts;
+    m1 = t1;
+    m2 = t2;
+  }
+}
+
 __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* red) {
   const uint32_t s = wave_sum(v);
   const uint32_t w = threadIdx.x >> 6;
@@ -193,6 +246,54 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* red) {
   for (int k = 0; k < WAVES; ++k) t += red[k];
   __syncthreads();
   return t;
+}
+
+// Two independent in-place exclusive scans, of a[0..na) and b[0..nb), with
+// one pair of barriers; a[na] and b[nb] receive the totals.  `red` is LDS
+// scratch of 2*WAVES words.
+__device__ __forceinline__ void block_exclusive_scan2(uint32_t* a, uint32_t na, uint32_t* b,
+                                                      uint32_t nb, uint32_t* red) {
+  const uint32_t pa = (na + NSGC_BLOCK - 1) / NSGC_BLOCK, pb = (nb + NSGC_BLOCK - 1) / NSGC_BLOCK;
+  const uint32_t a0 = min(na, threadIdx.x * pa), a1 = min(na, a0 + pa);
+  const uint32_t b0 = min(nb, threadIdx.x * pb), b1 = min(nb, b0 + pb);
+  uint32_t sa = 0, sb = 0;
+  for (uint32_t i = a0; i < a1; ++i) sa += a[i];
+  for (uint32_t i = b0; i < b1; ++i) sb += b[i];
+  const uint32_t ia = wave_inclusive_scan(sa), ib = wave_inclusive_scan(sb);
+  const uint32_t w = threadIdx.x >> 6;
+  if (lane_id() == 63) {
+    red[w] = ia;
+    red[WAVES + w] = ib;
+  }
+  __syncthreads();
+  uint32_t ba = 0, ta = 0, bb = 0, tb = 0;
+#pragma unroll
+  for (int k = 0; k < WAVES; ++k) {
+    const uint32_t x = red[k], y = red[WAVES + k];
+    if (uint32_t(k) < w) {
+      ba += x;
+      bb += y;
+    }
+    ta += x;
+    tb += y;
+  }
+  uint32_t run = ba + ia - sa;
+  for (uint32_t i = a0; i < a1; ++i) {
+    const uint32_t x = a[i];
+    a[i] = run;
+    run += x;
+  }
+  run = bb + ib - sb;
+  for (uint32_t i = b0; i < b1; ++i) {
+    const uint32_t x = b[i];
+    b[i] = run;
+    run += x;
+  }
+  if (threadIdx.x == 0) {
+    a[na] = ta;
+    b[nb] = tb;
+  }
+  __syncthreads();
 }
 
 // In-place exclusive scan of a[0..n) in LDS; a[n] receives the total, which is

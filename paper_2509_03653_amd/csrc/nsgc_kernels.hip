@@ -467,17 +467,16 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
     const NSGC_GLOBAL uint32_t* tm1 = tm0 + nt;                                      // bucket b+1
     NSGC_GLOBAL uint32_t* rec = gptr(P->lbmeta) + W.lbmeta;
 
+    // The emission base of bucket b (packets of the window in link buckets
+    // below b) is the sum of b's starts over the tiles: summed while the
+    // first gather loads them.
     if (threadIdx.x == 0) misc[4] = 0;
-    __syncthreads();
-    {  // emission base: packets of the window in link buckets below b
-      uint32_t below = 0;
-      for (uint32_t t = threadIdx.x; t < nt; t += NSGC_BLOCK) below += tm0[t];
-      below = wave_sum(below);
-      if (lane_id() == 0 && below) lds_add(&misc[4], below);
-    }
+    uint32_t below = 0;
+    bool base_pending = true;
 
     auto seg = [&](uint32_t t, u64& sbase, uint32_t& len) {
       const uint32_t s0 = tm0[t], s1 = tm1[t];
+      if (base_pending) below += s0;
       sbase = u64(t) * T + s0;
       len = s1 - s0;
     };
@@ -544,6 +543,11 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
           if (fresh[u]) occ[at] = uint32_t(slot[u]);
         }
       });
+      if (base_pending) {   // visible after the barriers before any emission
+        base_pending = false;
+        below = wave_sum(below);
+        if (lane_id() == 0 && below) lds_add(&misc[4], below);
+      }
     };
 
     // Count (or, with cursors, write) the links per row and column bucket.
@@ -730,8 +734,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
       __syncthreads();
     };
     auto publish = [&]() {
-      block_exclusive_scan(histR, R, st.red);
-      block_exclusive_scan(histC, C, st.red);
+      block_exclusive_scan2(histR, R, histC, C, st.red);
       for (uint32_t i = threadIdx.x; i <= R; i += NSGC_BLOCK) rec[B + u64(i) * B + b] = histR[i];
       for (uint32_t i = threadIdx.x; i <= C; i += NSGC_BLOCK)
         rec[B + u64(R + 1) * B + u64(i) * B + b] = histC[i];
@@ -820,9 +823,9 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
     }
     if (threadIdx.x == 0) rec[b] = misc[4];
 
-    // bucket totals -> window statistics 0..2
-    block_sum_max(sum, mx, st.red);
-    const uint32_t nlinks = block_sum(links, st.red);
+    // bucket totals -> window statistics 0..2 (thread 0 holds them)
+    uint32_t nlinks = links;
+    block_sum2_max_to0(sum, nlinks, mx, st.red);
     if (threadIdx.x == 0) {
       NSGC_GLOBAL u64* o = gptr(P->out) + u64(W.out_index) * 9;
       if (abandoned)
@@ -1000,9 +1003,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
       }
       if (!failed) break;
     }
-    block_sum_max(n, mp, st.red);
-    uint32_t zero = 0;
-    block_sum_max(zero, ml, st.red);
+    block_sum_max2_to0(n, mp, ml, st.red);   // thread 0 holds the bucket's totals
     if (threadIdx.x == 0) {
       NSGC_GLOBAL u64* o = gptr(P->out) + u64(W.out_index) * 9 + (is_row ? 3 : 6);
       if (abandoned)
