@@ -524,23 +524,6 @@ __device__ __forceinline__ bool cas_insert(K* tk, uint32_t mask, const K (&key)[
   return !gave_up;
 }
 
-// Largest i < cn with off[i] <= j[u] for U queries at once (off non-decreasing,
-// off[0] = 0): a branch-free binary search whose LDS reads for the U queries
-// are issued together each round.
-template <int U>
-__device__ __forceinline__ void lockstep_owner(const uint32_t* off, uint32_t cn,
-                                               const uint32_t (&j)[U], uint32_t (&idx)[U]) {
-#pragma unroll
-  for (int u = 0; u < U; ++u) idx[u] = 0;
-  for (uint32_t s = cn > 1 ? (1u << (31 - __clz(cn - 1))) : 0u; s; s >>= 1) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t c = idx[u] + s;
-      if (c < cn && off[c] <= j[u]) idx[u] = c;
-    }
-  }
-}
-
 __device__ __forceinline__ uint32_t lds_add(uint32_t* p, uint32_t v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }

@@ -78,8 +78,6 @@ constexpr u64 NSGC_INVALID_BIT = 1ull << 63;
 // VGPRs, i.e. two 512-thread workgroups per compute unit.
 constexpr int LINK_MAXU = 4;
 constexpr int RC_MAXU = 4;
-// Phase C stages fewer segments at a time so that three workgroups fit a CU.
-constexpr uint32_t RC_MAXSEG = 256;
 // Links a thread holds while phase B combines them per source and
 // destination: the link table has at most LK * NSGC_BLOCK slots.
 constexpr int LK = 8;
@@ -346,51 +344,86 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* _
 }
 
 // ---------------------------------------------------------------------------
-// Shared machinery of phases B and C: visit the elements of up to
-// MAXSEG segments at a time, up to U per thread per round.  `seg(i,
-// base, len)` describes segment i; `fn(pos, ok)` receives arrays of the
-// round's flat positions (pos[u] valid when ok[u]; the array length is the
-// round's unroll) with the whole wavefront active.
+// Shared machinery of phases B and C: visit the elements of `nseg` segments
+// (`seg(i, base, len)` describes segment i) wavefront by wavefront.
+//
+// Wavefront w takes segments w, w + WAVES, w + 2 WAVES, ... of each group of
+// 64 * WAVES segments; its lanes load the descriptions of the wave's (up to
+// 64) segments at once, and the wave walks them in chunks of 64 consecutive
+// elements (lane = offset in the chunk), up to MAXU chunks per round.  There
+// is no LDS staging, scan or per-element segment search, and no barrier
+// until the one at the end, so waves proceed independently.  `fn(pos, ok)`
+// receives the round's positions (pos[u] valid when ok[u]; the array length
+// is the round's unroll) with the whole wavefront active; it must not use
+// workgroup barriers.
 // ---------------------------------------------------------------------------
 
-struct SegStage {
-  u64* base;       // [MAXSEG]
-  uint32_t* off;   // [MAXSEG + 1]
-  uint32_t* red;   // [2 * WAVES]
-};
+__device__ __forceinline__ u64 readlane64(u64 v, uint32_t k) {
+  return (u64(readlane(uint32_t(v >> 32), int(k))) << 32) | readlane(uint32_t(v), int(k));
+}
 
-template <int MAXU, uint32_t MAXSEG, class SegFn, class BatchFn>
-__device__ __forceinline__ void gather_segments(uint32_t nseg, const SegStage& st, SegFn seg,
-                                                BatchFn fn) {
-  for (uint32_t c0 = 0; c0 < nseg; c0 += MAXSEG) {
-    const uint32_t cn = min(MAXSEG, nseg - c0);
-    for (uint32_t i = threadIdx.x; i < cn; i += NSGC_BLOCK) {
-      u64 b;
-      uint32_t l;
-      seg(c0 + i, b, l);
-      st.base[i] = b;
-      st.off[i] = l;
+// Rounds over `total` chunks (uniform across the wavefront, not the block):
+// body(integral_constant<int, UU>) with the smallest UU of 4, 2, 1 (at most
+// MAXU) that covers what is left.
+template <int MAXU, class Body>
+__device__ __forceinline__ void for_chunk_rounds(uint32_t total, Body&& body) {
+  static_assert(MAXU == 8 || MAXU == 4 || MAXU == 2 || MAXU == 1, "unroll");
+  for (uint32_t c = 0; c < total;) {
+    const uint32_t rem = total - c;
+    if (MAXU >= 8 && rem > 4) {
+      body(std::integral_constant<int, (MAXU >= 8 ? 8 : 1)>());
+      c += 8;
+    } else if (MAXU >= 4 && rem > 2) {
+      body(std::integral_constant<int, (MAXU >= 4 ? 4 : 1)>());
+      c += 4;
+    } else if (MAXU >= 2 && rem > 1) {
+      body(std::integral_constant<int, (MAXU >= 2 ? 2 : 1)>());
+      c += 2;
+    } else {
+      body(std::integral_constant<int, 1>());
+      c += 1;
     }
-    __syncthreads();
-    const uint32_t total = block_exclusive_scan(st.off, cn, st.red);
-    for_rounds<MAXU>(total, [&](uint32_t j0, auto uc) {
+  }
+}
+
+template <int MAXU, class SegFn, class BatchFn>
+__device__ __forceinline__ void gather_by_wave(uint32_t nseg, SegFn seg, BatchFn fn) {
+  const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+  constexpr uint32_t GROUP = 64u * uint32_t(WAVES);
+  for (uint32_t g0 = 0; g0 < nseg; g0 += GROUP) {
+    const uint32_t si = g0 + w + uint32_t(WAVES) * lane;   // this lane's segment
+    u64 mybase = 0;
+    uint32_t mylen = 0;
+    if (si < nseg) seg(si, mybase, mylen);
+    const uint32_t nk = g0 + w < nseg ? min(64u, (nseg - g0 - w + WAVES - 1) / WAVES) : 0u;
+    const uint32_t total = wave_sum((mylen + 63u) >> 6);   // the wave's chunks
+    uint32_t k = 0, off = 0;                                 // uniform cursor
+    while (k < nk && readlane(mylen, int(k)) == 0) ++k;
+    for_chunk_rounds<MAXU>(total, [&](auto uc) {
       constexpr int U = decltype(uc)::value;
-      uint32_t j[U], idx[U];
-      bool ok[U];
       u64 pos[U];
+      bool ok[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        j[u] = j0 + u * NSGC_BLOCK + threadIdx.x;
-        ok[u] = j[u] < total;
-        if (!ok[u]) j[u] = 0;
+        if (k < nk) {
+          const uint32_t len = readlane(mylen, int(k));
+          pos[u] = readlane64(mybase, k) + off + lane;
+          ok[u] = off + lane < len;
+          off += 64;
+          if (off >= len) {
+            off = 0;
+            ++k;
+            while (k < nk && readlane(mylen, int(k)) == 0) ++k;
+          }
+        } else {
+          pos[u] = 0;
+          ok[u] = false;
+        }
       }
-      lockstep_owner<U>(st.off, cn, j, idx);
-#pragma unroll
-      for (int u = 0; u < U; ++u) pos[u] = st.base[idx[u]] + (j[u] - st.off[idx[u]]);
       fn(pos, ok);
     });
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -419,8 +452,8 @@ __device__ __forceinline__ void gather_segments(uint32_t nseg, const SegStage& s
 
 size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_buckets) {
   const size_t S = size_t(1) << slots_log2;
-  return align16(S * 8) + align16(S * 4) + align16(S * 4) + align16(NSGC_MAX_SEG * 8) +
-         align16((NSGC_MAX_SEG + 1) * 4) + 2 * align16((max_buckets + 1) * 4) + 256;
+  return align16(S * 8) + align16(S * 4) + align16(S * 4) + 2 * align16((max_buckets + 1) * 4) +
+         256;
 }
 
 // COMBINE selects the single-sweep emission: per link (false) or combined per
@@ -436,9 +469,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
   u64* tk = reinterpret_cast<u64*>(p);                 p += align16(S * 8);
   uint32_t* tc = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
   uint32_t* occ = reinterpret_cast<uint32_t*>(p);      p += align16(S * 4);
-  SegStage st;
-  st.base = reinterpret_cast<u64*>(p);                 p += align16(NSGC_MAX_SEG * 8);
-  st.off = reinterpret_cast<uint32_t*>(p);             p += align16((NSGC_MAX_SEG + 1) * 4);
+  struct { uint32_t* red; } st;                        // reduction scratch (in misc)
   uint32_t* histR = reinterpret_cast<uint32_t*>(p);    p += align16((max_buckets + 1) * 4);
   uint32_t* histC = reinterpret_cast<uint32_t*>(p);    p += align16((max_buckets + 1) * 4);
   uint32_t* misc = reinterpret_cast<uint32_t*>(p);
@@ -498,7 +529,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
     auto build = [&](uint32_t logS, uint32_t sw) {
       if (threadIdx.x < 2) misc[threadIdx.x] = 0;
       __syncthreads();
-      gather_segments<LINK_MAXU, NSGC_MAX_SEG>(nt, st, seg, [&](const auto& pos, const auto& okin) {
+      gather_by_wave<LINK_MAXU>(nt, seg, [&](const auto& pos, const auto& okin) {
         constexpr int U = array_len<decltype(pos)>();
         u64 key[U];
         uint32_t h[U], add[U];
@@ -852,7 +883,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 
 size_t lds_rc_bytes(uint32_t slots_log2) {
   const size_t S = size_t(1) << slots_log2;
-  return align16(S * 4) * 3 + align16(RC_MAXSEG * 8) + align16((RC_MAXSEG + 1) * 4) + 256;
+  return align16(S * 4) * 3 + 256;
 }
 
 __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_rowcol(nsgc_dev_plan* P) {
@@ -862,9 +893,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
   uint32_t* tk = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
   uint32_t* ta = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
   uint32_t* tb = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
-  SegStage st;
-  st.base = reinterpret_cast<u64*>(p);                 p += align16(RC_MAXSEG * 8);
-  st.off = reinterpret_cast<uint32_t*>(p);             p += align16((RC_MAXSEG + 1) * 4);
+  struct { uint32_t* red; } st;                        // reduction scratch (in misc)
   uint32_t* misc = reinterpret_cast<uint32_t*>(p);     // [0] fail flag, [2,3] special id,
                                                        // [7] queue slot
   st.red = misc + 8;
@@ -932,7 +961,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
     auto build = [&](uint32_t logS, uint32_t sw) {
       if (threadIdx.x < 4) misc[threadIdx.x] = 0;
       __syncthreads();
-      gather_segments<RC_MAXU, RC_MAXSEG>(B, st, seg, [&](const auto& pos, const auto& okin) {
+      gather_by_wave<RC_MAXU>(B, seg, [&](const auto& pos, const auto& okin) {
         constexpr int U = array_len<decltype(pos)>();
         uint32_t id[U], h[U], pk[U], ln[U];
         bool ok[U];

@@ -31,7 +31,6 @@
 #include <stdint.h>
 
 #define NSGC_BLOCK 512          // threads per workgroup in every kernel
-#define NSGC_MAX_SEG 512        // segments staged in LDS at a time (phases B, C)
 #define NSGC_UNROLL 8           // elements per thread in flight in the B/C gathers
 
 // A phase-B emission entry packs an id with the links and packets it stands
