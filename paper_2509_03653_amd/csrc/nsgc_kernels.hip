@@ -386,19 +386,25 @@ __device__ __forceinline__ void for_chunk_rounds(uint32_t total, Body&& body) {
   }
 }
 
+// Keeps a wave-uniform value in a scalar register (the compiler cannot always
+// prove uniformity of values derived from threadIdx.x / 64).
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_readfirstlane(int(v)));
+}
+
 template <int MAXU, class SegFn, class BatchFn>
 __device__ __forceinline__ void gather_by_wave(uint32_t nseg, SegFn seg, BatchFn fn) {
-  const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+  const uint32_t w = uniform(threadIdx.x >> 6), lane = lane_id();
   constexpr uint32_t GROUP = 64u * uint32_t(WAVES);
   for (uint32_t g0 = 0; g0 < nseg; g0 += GROUP) {
     const uint32_t si = g0 + w + uint32_t(WAVES) * lane;   // this lane's segment
     u64 mybase = 0;
     uint32_t mylen = 0;
     if (si < nseg) seg(si, mybase, mylen);
-    const uint32_t nk = g0 + w < nseg ? min(64u, (nseg - g0 - w + WAVES - 1) / WAVES) : 0u;
-    const uint32_t total = wave_sum((mylen + 63u) >> 6);   // the wave's chunks
-    uint32_t k = 0, off = 0;                                 // uniform cursor
-    while (k < nk && readlane(mylen, int(k)) == 0) ++k;
+    const uint32_t nk = uniform(g0 + w < nseg ? min(64u, (nseg - g0 - w + WAVES - 1) / WAVES) : 0u);
+    const uint32_t total = uniform(wave_sum((mylen + 63u) >> 6));   // the wave's chunks
+    uint32_t k = 0, off = 0;                                          // uniform cursor
+    while (k < nk && readlane(mylen, int(k)) == 0) k = uniform(k + 1);
     for_chunk_rounds<MAXU>(total, [&](auto uc) {
       constexpr int U = decltype(uc)::value;
       u64 pos[U];
@@ -409,11 +415,11 @@ __device__ __forceinline__ void gather_by_wave(uint32_t nseg, SegFn seg, BatchFn
           const uint32_t len = readlane(mylen, int(k));
           pos[u] = readlane64(mybase, k) + off + lane;
           ok[u] = off + lane < len;
-          off += 64;
+          off = uniform(off + 64);
           if (off >= len) {
             off = 0;
-            ++k;
-            while (k < nk && readlane(mylen, int(k)) == 0) ++k;
+            k = uniform(k + 1);
+            while (k < nk && readlane(mylen, int(k)) == 0) k = uniform(k + 1);
           }
         } else {
           pos[u] = 0;
@@ -535,7 +541,10 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
         uint32_t h[U], add[U];
         bool ok[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) key[u] = okin[u] ? keys[pos[u]] : 0ull;
+        for (int u = 0; u < U; ++u) {   // unconditional load (position 0 exists), then mask
+          const u64 kk = keys[okin[u] ? pos[u] : 0ull];
+          key[u] = okin[u] ? kk : 0ull;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const u64 hh = link_hash(key[u]);
@@ -967,7 +976,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const u64 e = okin[u] ? em[pos[u]] : 0ull;
+          const u64 ee = em[okin[u] ? pos[u] : 0ull];   // position 0 exists; masked below
+          const u64 e = okin[u] ? ee : 0ull;
           id[u] = uint32_t(e >> 32);
           pk[u] = uint32_t(e) & ENT_PMAX;
           ln[u] = uint32_t(e) >> NSGC_ENT_PACKET_BITS;
