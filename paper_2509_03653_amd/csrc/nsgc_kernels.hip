@@ -77,7 +77,7 @@ constexpr u64 NSGC_INVALID_BIT = 1ull << 63;
 // Phase B holds 64-bit keys; four elements per thread keep it within 128
 // VGPRs, i.e. two 512-thread workgroups per compute unit.
 constexpr int LINK_MAXU = 4;
-constexpr int RC_MAXU = 4;
+constexpr int RC_MAXU = 8;
 // Links a thread holds while phase B combines them per source and
 // destination: the link table has at most LK * NSGC_BLOCK slots.
 constexpr int LK = 8;
