@@ -308,10 +308,6 @@ size_t workspace_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune
   return size_t(P * 24 + (tilemeta + lbmeta + W) * 4 + 8 * 256);
 }
 
-size_t plan_bound(int64_t max_windows) {
-  const size_t W = size_t(std::max<int64_t>(max_windows, 1));
-  return 1024 + W * (sizeof(nsgc_small_desc) + sizeof(nsgc_win_desc) + 12) + 1024;
-}
 
 }  // namespace
 
@@ -433,14 +429,14 @@ int nsgc_reserve(int64_t max_packets, int64_t max_windows, void* stream) {
   const hipStream_t s = static_cast<hipStream_t>(stream);
   Slot* sl = nullptr;
   if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
-  if ((rc = ensure_device(&sl->plan_dev, &sl->plan_cap, plan_bound(max_windows), s)) != NSGC_OK)
-    return rc;
+  const size_t pb = plan_bound(max_packets, max_windows, t);
+  if ((rc = ensure_device(&sl->plan_dev, &sl->plan_cap, pb, s)) != NSGC_OK) return rc;
   if ((rc = ensure_device(&sl->ws, &sl->ws_cap, workspace_bound(max_packets, max_windows, t), s)) !=
       NSGC_OK)
     return rc;
   for (int k = 0; k < kStages; ++k) {
     int idx = 0;
-    if ((rc = take_stage(sl, plan_bound(max_windows), s, &idx)) != NSGC_OK) return rc;
+    if ((rc = take_stage(sl, pb, s, &idx)) != NSGC_OK) return rc;
   }
   return NSGC_OK;
 }
@@ -616,7 +612,7 @@ int nsgc_graph_create(int64_t max_packets, int64_t max_windows, nsgc_graph** out
     destroy_graph(g);
     return hip_fail(e);
   }
-  const size_t pb = plan_bound(max_windows);
+  const size_t pb = plan_bound(max_packets, max_windows, g->tune);
   for (auto& in : g->inst) {
     void* p = nullptr;
     if ((e = hipMalloc(&p, pb)) != hipSuccess) { destroy_graph(g); return NSGC_ERR_NO_MEMORY; }

@@ -45,6 +45,30 @@ __device__ __forceinline__ T gload(const T* p) {
 
 typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
 
+// Load through the scalar data cache: for plan data that no kernel writes
+// while it runs, read at a wave-uniform address.  These loads count against
+// the LDS/scalar wait counter, not the vector memory one, so they do not wait
+// for the wave's outstanding global stores.
+template <class T>
+__device__ __forceinline__ T sload(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)(p);
+}
+
+// A window descriptor read as sixteen 32-bit words through sload (the scalar
+// cache has no byte loads).
+template <class T>
+__device__ __forceinline__ T sload_words(const T* p) {
+  static_assert(sizeof(T) % 16 == 0, "descriptor size must be a multiple of 16");
+  constexpr int N = int(sizeof(T) / 16);
+  const __attribute__((address_space(4))) v4u32* q = (const __attribute__((address_space(4))) v4u32*)(p);
+  v4u32 raw[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) raw[i] = q[i];
+  T out;
+  __builtin_memcpy(&out, raw, sizeof(T));
+  return out;
+}
+
 // ---- hashing: invertible xorshift / odd-multiply mixers ------------------
 // Bijections, so the bucket, sweep and slot bits taken from one mix of a key
 // can always be refined until a group holds a single key.

@@ -494,9 +494,10 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
   const uint32_t items = P->itemsB;
   ItemQueue q{gptr(&P->queue[1]), misc + 7, 0};
   for (uint32_t item = q.first(items); item < items; item = q.next(items)) {
-    const uint32_t wi = owner_of_wave(gptr(P->prefB), P->num_part, item);
-    const nsgc_win_desc W = gload(P->win + wi);
-    const uint32_t b = item - gptr(P->prefB)[wi];
+    const uint32_t it = uniform(item);
+    const uint32_t wi = sload(P->itemwinB + it);
+    const nsgc_win_desc W = sload_words(P->win + wi);
+    const uint32_t b = it - sload(P->prefB + wi);
     const uint32_t B = 1u << W.logB, R = 1u << W.logR, C = 1u << W.logC;
     const uint32_t nt = W.ntiles;
     const NSGC_GLOBAL u64* keys = gptr(P->keys) + W.ws;
@@ -916,9 +917,10 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
   const uint32_t items = P->itemsC;
   ItemQueue q{gptr(&P->queue[2]), misc + 7, 0};
   for (uint32_t item = q.first(items); item < items; item = q.next(items)) {
-    const uint32_t wi = owner_of_wave(gptr(P->prefC), P->num_part, item);
-    const nsgc_win_desc W = gload(P->win + wi);
-    const uint32_t k = item - gptr(P->prefC)[wi];
+    const uint32_t it = uniform(item);
+    const uint32_t wi = sload(P->itemwinC + it);
+    const nsgc_win_desc W = sload_words(P->win + wi);
+    const uint32_t k = it - sload(P->prefC + wi);
     const uint32_t B = 1u << W.logB, R = 1u << W.logR;
     const bool is_row = k < R;
     const uint32_t bucket = is_row ? k : k - R;

@@ -89,6 +89,8 @@ struct nsgc_dev_plan {          // header of the device plan buffer
   const uint32_t* prefA;        // [num_part + 1] first phase-A item of each window
   const uint32_t* prefB;        // [num_part + 1] first phase-B item
   const uint32_t* prefC;        // [num_part + 1] first phase-C item
+  const uint32_t* itemwinB;     // [itemsB] window (index among partitioned) of each phase-B item
+  const uint32_t* itemwinC;     // [itemsC] window of each phase-C item
   uint32_t num_small;
   uint32_t num_part;
   uint32_t itemsA, itemsB, itemsC;

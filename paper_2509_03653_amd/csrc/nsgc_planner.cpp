@@ -68,6 +68,8 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
   p->prefA.clear();
   p->prefB.clear();
   p->prefC.clear();
+  p->itemwinB.clear();
+  p->itemwinC.clear();
   p->tier.assign(size_t(num_windows), 0);
   p->ws_elems = p->tilemeta_words = p->lbmeta_words = 0;
   p->tile_log2 = uint32_t(tune.tile_log2);
@@ -115,6 +117,9 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
     p->prefA.push_back(uint32_t(a));
     p->prefB.push_back(uint32_t(b));
     p->prefC.push_back(uint32_t(c));
+    const uint32_t wi = uint32_t(p->win.size());
+    p->itemwinB.insert(p->itemwinB.end(), size_t(B), wi);
+    p->itemwinC.insert(p->itemwinC.end(), size_t(R + C), wi);
     a += d.ntiles;
     b += B;
     c += R + C;
@@ -146,9 +151,9 @@ WsLayout HostPlan::layout() const {
 
 namespace {
 struct PlanOffsets {
-  size_t small, win, prefA, prefB, prefC, total;
+  size_t small, win, prefA, prefB, prefC, itemwinB, itemwinC, total;
 };
-PlanOffsets plan_offsets(size_t ns, size_t nm) {
+PlanOffsets plan_offsets(size_t ns, size_t nm, size_t nb, size_t nc) {
   PlanOffsets o;
   size_t x = align_up(sizeof(nsgc_dev_plan), 64);
   o.small = x; x = align_up(x + ns * sizeof(nsgc_small_desc), 64);
@@ -156,16 +161,37 @@ PlanOffsets plan_offsets(size_t ns, size_t nm) {
   o.prefA = x; x = align_up(x + (nm + 1) * 4, 64);
   o.prefB = x; x = align_up(x + (nm + 1) * 4, 64);
   o.prefC = x; x = align_up(x + (nm + 1) * 4, 64);
+  o.itemwinB = x; x = align_up(x + nb * 4, 64);
+  o.itemwinC = x; x = align_up(x + nc * 4, 64);
   o.total = x;
   return o;
 }
 }  // namespace
 
-size_t HostPlan::plan_bytes() const { return plan_offsets(small.size(), win.size()).total; }
+size_t HostPlan::plan_bytes() const {
+  return plan_offsets(small.size(), win.size(), itemwinB.size(), itemwinC.size()).total;
+}
+
+size_t plan_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune& t) {
+  const uint64_t P = uint64_t(std::max<int64_t>(max_packets, 0));
+  const uint64_t W = uint64_t(std::max<int64_t>(max_windows, 1));
+  uint64_t lt = ~uint64_t(0), rt = ~uint64_t(0);
+  for (int k = 0; k <= 32; ++k) {
+    lt = std::min<uint64_t>(lt, uint64_t(t.cls[k].link_target));
+    rt = std::min<uint64_t>(rt, uint64_t(std::min(t.cls[k].row_target, t.cls[k].col_target)));
+  }
+  // A bucket count is the power of two at or above ceil(n_w / target) < n_w /
+  // target + 1, so B_w < 2 n_w / lt + 2 and R_w + C_w < 4 n_w / rt + 4; each
+  // count is also at most 2^max_buckets_log2 per window.
+  const uint64_t cap = uint64_t(1) << t.max_buckets_log2;
+  const uint64_t nb = std::min<uint64_t>(2 * P / lt + 2 * W, W * cap);
+  const uint64_t nc = std::min<uint64_t>(4 * P / rt + 4 * W, 2 * W * cap);
+  return plan_offsets(size_t(W), size_t(W), size_t(nb), size_t(nc)).total + 1024;
+}
 
 void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const uint32_t* src,
                          const uint32_t* dst, void* out) const {
-  const PlanOffsets o = plan_offsets(small.size(), win.size());
+  const PlanOffsets o = plan_offsets(small.size(), win.size(), itemwinB.size(), itemwinC.size());
   const WsLayout L = layout();
   char* base = static_cast<char*>(buf);
   std::memset(base, 0, align_up(sizeof(nsgc_dev_plan), 64));
@@ -185,6 +211,8 @@ void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const ui
   h.prefA = reinterpret_cast<const uint32_t*>(dev_plan + o.prefA);
   h.prefB = reinterpret_cast<const uint32_t*>(dev_plan + o.prefB);
   h.prefC = reinterpret_cast<const uint32_t*>(dev_plan + o.prefC);
+  h.itemwinB = reinterpret_cast<const uint32_t*>(dev_plan + o.itemwinB);
+  h.itemwinC = reinterpret_cast<const uint32_t*>(dev_plan + o.itemwinC);
   h.num_small = uint32_t(small.size());
   h.num_part = uint32_t(win.size());
   h.itemsA = itemsA;
@@ -202,6 +230,8 @@ void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const ui
   std::memcpy(base + o.prefA, prefA.data(), prefA.size() * 4);
   std::memcpy(base + o.prefB, prefB.data(), prefB.size() * 4);
   std::memcpy(base + o.prefC, prefC.data(), prefC.size() * 4);
+  if (!itemwinB.empty()) std::memcpy(base + o.itemwinB, itemwinB.data(), itemwinB.size() * 4);
+  if (!itemwinC.empty()) std::memcpy(base + o.itemwinC, itemwinC.data(), itemwinC.size() * 4);
 }
 
 }  // namespace nsgc

@@ -23,6 +23,7 @@ struct HostPlan {
   std::vector<nsgc_small_desc> small;
   std::vector<nsgc_win_desc> win;
   std::vector<uint32_t> prefA, prefB, prefC;
+  std::vector<uint32_t> itemwinB, itemwinC;   // window of each phase-B / phase-C item
   int64_t ws_elems = 0;        // packets of the partitioned windows
   int64_t tilemeta_words = 0;  // u32 words of tile bucket starts
   int64_t lbmeta_words = 0;    // u32 words of link-bucket records
@@ -53,6 +54,10 @@ int check_tune(const nsgc_tune& t);
 
 // Smallest k with 2^k >= x (x >= 1).
 int ceil_log2(uint64_t x);
+
+// Upper bound of plan_bytes() for any batch of <= max_packets packets in <=
+// max_windows windows planned with `t`.
+size_t plan_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune& t);
 
 
 }  // namespace nsgc
