@@ -198,6 +198,29 @@ def test_graph_reuse_with_different_batches():
         g.close()
 
 
+def test_graph_plan_holds_many_items_per_window():
+    # tiny bucket targets and the largest bucket cap give thousands of phase-B
+    # and phase-C items per window: the graph's plan buffer, sized when the
+    # graph is created, must hold their per-item tables
+    import torch
+    base = nsgc.default_tune().to_dict()
+    base.update(cls=[[64, 64, 64]] * 33, max_buckets_log2=12, small_max=0)
+    nsgc.set_tune(nsgc.Tune.from_dict(base))
+    g = nsgc.Graph(1 << 20, 4)
+    try:
+        for seed, sizes in ((1, [1 << 18, 1 << 18, 1 << 18, 1 << 18]), (2, [1 << 20]),
+                            (3, [5, 1 << 19, 3, (1 << 19) - 8])):
+            off = synth.offsets_from_sizes(sizes)
+            wl = synth.zipf_batch(seed=seed, num_windows=1, log2_window=4)
+            src, dst = synth.fill(off, seed, wl.src_dist, wl.dst_dist)
+            want = oracle.window_stats(src, dst, off, threads=4)
+            say(f"[gpu] graph, many items per window, seed {seed}")
+            assert_same(gpu_stats(src, dst, off, "graph", graph=g), want, f"many items {seed}")
+        torch.cuda.synchronize()
+    finally:
+        g.close()
+
+
 def test_stream_argument_and_out_reuse():
     import torch
     wl = synth.zipf_batch(seed=8, num_windows=3, log2_window=14)
