@@ -21,7 +21,7 @@ int ceil_log2(uint64_t x) {
 void default_tune(nsgc_tune* t) {
   std::memset(t, 0, sizeof(*t));
   t->small_max = 1024;
-  t->tile_log2 = 13;
+  t->tile_log2 = 14;
   t->link_slots_log2 = 12;
   t->rc_slots_log2 = 12;
   t->blocks_per_cu = 3;

@@ -28,7 +28,7 @@ struct HostPlan {
   int64_t tilemeta_words = 0;  // u32 words of tile bucket starts
   int64_t lbmeta_words = 0;    // u32 words of link-bucket records
   uint32_t itemsA = 0, itemsB = 0, itemsC = 0;
-  uint32_t tile_log2 = 13, link_slots_log2 = 12, rc_slots_log2 = 12, small_slots_log2 = 11;
+  uint32_t tile_log2 = 14, link_slots_log2 = 12, rc_slots_log2 = 12, small_slots_log2 = 11;
   uint32_t max_sweeps_log2 = 24;
   uint32_t combine_probes = 0;
   std::vector<int32_t> tier;   // per window: 0 empty, 1 small, 2 partitioned
