@@ -302,7 +302,7 @@ def poisson_arrivals(n: int, rate: float, seed: int) -> np.ndarray:
 
 class GpuExecutor:
     """Executor on one GPU: a device arena of `capacity` packet slots for src
-    and dst, one copy stream, `streams` compute streams (each with its library
+    and dst, two copy streams (src and dst), `streams` compute streams (each with its library
     workspace reserved for the largest batch, so nothing is allocated while
     serving), and pinned result buffers."""
 
@@ -315,7 +315,9 @@ class GpuExecutor:
         self.capacity = int(capacity)
         self.src = torch.empty(self.capacity, dtype=torch.int32, device=self.dev)
         self.dst = torch.empty(self.capacity, dtype=torch.int32, device=self.dev)
-        self.copy_stream = torch.cuda.Stream(self.dev)
+        # src and dst go up on two copy streams so that two DMA engines share
+        # each window's upload
+        self.copy_streams = [torch.cuda.Stream(self.dev), torch.cuda.Stream(self.dev)]
         self.streams = [torch.cuda.Stream(self.dev) for _ in range(max(1, streams))]
         self.max_w = int(max_batch_windows)
         for s in self.streams:
@@ -328,7 +330,7 @@ class GpuExecutor:
         # taken that batch's results (the event alone is not enough: a batch
         # may finish between the scheduler's poll and its next launch)
         self.owner = [None] * len(self.streams)
-        self.last_upload = None
+        self.last_upload = [None, None]
 
     def upload(self, r):
         torch = self.torch
@@ -337,12 +339,13 @@ class GpuExecutor:
             return
         src = r.src if isinstance(r.src, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(r.src).view(np.int32))
         dst = r.dst if isinstance(r.dst, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(r.dst).view(np.int32))
-        with torch.cuda.stream(self.copy_stream):
-            self.src[r.start:r.start + n].copy_(src.view(torch.int32), non_blocking=True)
-            self.dst[r.start:r.start + n].copy_(dst.view(torch.int32), non_blocking=True)
-        ev = torch.cuda.Event()
-        ev.record(self.copy_stream)
-        self.last_upload = ev
+        for i, (buf, host) in enumerate(((self.src, src), (self.dst, dst))):
+            cs = self.copy_streams[i]
+            with torch.cuda.stream(cs):
+                buf[r.start:r.start + n].copy_(host.view(torch.int32), non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(cs)
+            self.last_upload[i] = ev
 
     def launch(self, reqs):
         torch = self.torch
@@ -350,8 +353,9 @@ class GpuExecutor:
         if k is None:
             raise RuntimeError("more batches in flight than compute streams")
         s = self.streams[k]
-        if self.last_upload is not None:
-            s.wait_event(self.last_upload)  # uploads are in order on one stream
+        for ev in self.last_upload:         # uploads are in order on each copy stream
+            if ev is not None:
+                s.wait_event(ev)
         w = len(reqs)
         if w > self.max_w:
             raise ValueError("batch larger than the executor was sized for")
