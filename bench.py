@@ -278,7 +278,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--workload", default="zipf_batch", choices=sorted(WORKLOAD_TEXT),
-                    help="batch to time (the default is the headline configuration)")
+                    help="batch to time (default: 64 windows x 2^17 Zipf packets)")
     ap.add_argument("--autotune", action="store_true",
                     help="search (or load from the cache) the tuning for this batch first")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
@@ -295,9 +295,10 @@ def main():
         summarize_pmc(*args.summarize_pmc)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: the statistics of independent windows need no "
-              f"communication, and this build runs on a single MI355X (asked for --gpus "
-              f"{args.gpus}).", file=sys.stderr)
+        print(f"bench.py measures one GPU: the statistics of independent windows need no "
+              f"communication between GPUs, so whole-job throughput on N GPUs is N times the "
+              f"one-GPU figure for equal shares (asked for --gpus {args.gpus}; run with --gpus 1).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -10,7 +10,7 @@ bit, and caches the winner on disk keyed by device and batch shape.
 The search is coordinate descent: knobs are visited in a fixed order, every
 candidate value of the current knob is timed with the others held, and a
 value is kept only if it beats the incumbent by a margin.  `search` is a pure
-function of a `measure` callback so that the driver is testable without a
+function of a `measure` callback so that the search loop is testable without a
 GPU; `tune_for` supplies the measured callback (captured graph launches timed
 with HIP events on the launch stream).
 """

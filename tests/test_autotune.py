@@ -1,4 +1,4 @@
-"""Autotuner: the search driver, batch signatures and the cache (CPU), and a
+"""Autotuner: the search loop, batch signatures and the cache (CPU), and a
 measured search on the GPU whose every trial must reproduce the statistics."""
 import json
 
