@@ -284,6 +284,11 @@ def test_entities_match_numpy_unique():
     ud, cd = np.unique(dst, return_counts=True)
     np.testing.assert_array_equal(e["col_ids"], ud)
     np.testing.assert_array_equal(e["col_packets"], cd.astype(np.uint64))
+    # fan-out / fan-in: distinct links per source / destination
+    _, fo = np.unique(uk >> np.uint64(32), return_counts=True)
+    _, fi = np.unique(uk & np.uint64(0xFFFFFFFF), return_counts=True)
+    np.testing.assert_array_equal(e["row_links"], fo.astype(np.uint64))
+    np.testing.assert_array_equal(e["col_links"], fi.astype(np.uint64))
 
 
 def test_uniform_window_statistical_sanity():
