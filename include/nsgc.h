@@ -149,7 +149,9 @@ typedef struct nsgc_tune {
   int32_t rc_slots_log2;    /* LDS row/column table: 2^k slots (10..13) */
   int32_t blocks_per_cu;    /* persistent grid: workgroups per compute unit (1..16;
                                each kernel is capped at what can be resident) */
-  int32_t max_buckets_log2; /* cap on link/row/column buckets per window (0..12) */
+  int32_t max_link_buckets_log2;  /* cap on link buckets per window (0..12) */
+  int32_t max_rc_buckets_log2;    /* cap on row and on column buckets per
+                                     window (0..12) */
   int32_t max_sweeps_log2;  /* a bucket whose LDS table overflows is re-run in
                                2, 4, ... sweeps; past 2^max_sweeps_log2 sweeps
                                it is abandoned and its window marked invalid

@@ -89,14 +89,16 @@ class Tune(ctypes.Structure):
         ("link_slots_log2", ctypes.c_int32),
         ("rc_slots_log2", ctypes.c_int32),
         ("blocks_per_cu", ctypes.c_int32),
-        ("max_buckets_log2", ctypes.c_int32),
+        ("max_link_buckets_log2", ctypes.c_int32),
+        ("max_rc_buckets_log2", ctypes.c_int32),
         ("max_sweeps_log2", ctypes.c_int32),
         ("combine_probes", ctypes.c_int32),
         ("cls", TuneClass * 33),
     ]
 
     SCALARS = ("small_max", "tile_log2", "link_slots_log2", "rc_slots_log2",
-               "blocks_per_cu", "max_buckets_log2", "max_sweeps_log2", "combine_probes")
+               "blocks_per_cu", "max_link_buckets_log2", "max_rc_buckets_log2",
+               "max_sweeps_log2", "combine_probes")
 
     def to_dict(self) -> dict:
         d = {k: int(getattr(self, k)) for k in self.SCALARS}

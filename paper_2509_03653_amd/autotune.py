@@ -37,11 +37,12 @@ SPACE = (
     ("tile_log2", (12, 13, 14)),
     ("small_max", (256, 512, 1024, 2048)),
     ("link_scale", (0.5, 1.0, 2.0)),
+    ("max_link_buckets_log2", (10, 11, 12)),
     ("rc_scale", (0.5, 1.0, 2.0)),
     ("combine_probes", (0, 64)),
 )
 
-CACHE_VERSION = 1
+CACHE_VERSION = 2
 
 
 def size_classes(offsets) -> np.ndarray:

@@ -19,14 +19,14 @@
 
 namespace nsgc {
 hipError_t launch_small(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
-hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t max_buckets,
+hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t max_link_buckets,
                             uint32_t grid, size_t lds, hipStream_t s);
-hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_buckets, uint32_t grid,
+hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_buckets, uint32_t grid,
                         size_t lds, hipStream_t s);
 hipError_t launch_rowcol(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
 size_t lds_small_bytes(uint32_t slots_log2);
-size_t lds_part_bytes(uint32_t max_buckets, uint32_t tile_log2);
-size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_buckets);
+size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2);
+size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_rc_buckets);
 size_t lds_rc_bytes(uint32_t slots_log2);
 hipError_t allow_large_lds(size_t bytes);
 hipError_t resident_blocks(int which, uint32_t tile_log2, size_t lds, int* blocks);
@@ -171,7 +171,7 @@ struct Launch {
   uint32_t grid_small, grid_part, grid_link, grid_rc;  // persistent grid of each kernel
   bool combine;                                        // phase-B emission combines per id
   size_t lds_small, lds_part, lds_link, lds_rc;
-  uint32_t max_buckets;
+  uint32_t max_link_buckets, max_rc_buckets;
 };
 
 // Workgroups per CU that can actually be resident (registers and LDS), at
@@ -190,13 +190,14 @@ int resident_cap(DevCtx* c, int which, uint32_t tile_log2, size_t lds, int want,
 
 int launch_params(DevCtx* c, const nsgc_tune& t, Launch* out) {
   Launch L;
-  L.max_buckets = 1u << t.max_buckets_log2;
+  L.max_link_buckets = 1u << t.max_link_buckets_log2;
+  L.max_rc_buckets = 1u << t.max_rc_buckets_log2;
   const uint32_t small_log2 =
       uint32_t(std::max(ceil_log2(uint64_t(std::max(t.small_max, 1)) * 2), 6));
   const uint32_t tile = uint32_t(t.tile_log2);
   L.lds_small = lds_small_bytes(small_log2);
-  L.lds_part = lds_part_bytes(L.max_buckets, tile);
-  L.lds_link = lds_link_bytes(uint32_t(t.link_slots_log2), L.max_buckets);
+  L.lds_part = lds_part_bytes(L.max_link_buckets, tile);
+  L.lds_link = lds_link_bytes(uint32_t(t.link_slots_log2), L.max_rc_buckets);
   L.lds_rc = lds_rc_bytes(uint32_t(t.rc_slots_log2));
   const size_t m = std::max(std::max(L.lds_small, L.lds_part), std::max(L.lds_link, L.lds_rc));
   if (m > c->lds_limit) return NSGC_ERR_INVALID_ARG;
@@ -233,11 +234,11 @@ int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch
     NSGC_HIP(launch_small(dplan, grid(uint32_t(hp.small.size()), L.grid_small), L.lds_small, s));
   NSGC_HIP(mark(1));
   if (part)
-    NSGC_HIP(launch_partition(dplan, tile_log2, L.max_buckets, grid(hp.itemsA, L.grid_part),
+    NSGC_HIP(launch_partition(dplan, tile_log2, L.max_link_buckets, grid(hp.itemsA, L.grid_part),
                               L.lds_part, s));
   NSGC_HIP(mark(2));
   if (part)
-    NSGC_HIP(launch_links(dplan, L.combine, L.max_buckets, grid(hp.itemsB, L.grid_link),
+    NSGC_HIP(launch_links(dplan, L.combine, L.max_rc_buckets, grid(hp.itemsB, L.grid_link),
                           L.lds_link, s));
   NSGC_HIP(mark(3));
   if (part) NSGC_HIP(launch_rowcol(dplan, grid(hp.itemsC, L.grid_rc), L.lds_rc, s));
@@ -299,10 +300,11 @@ size_t workspace_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune
     lt = std::min(lt, t.cls[k].link_target);
     rt = std::min(rt, std::min(t.cls[k].row_target, t.cls[k].col_target));
   }
-  const uint64_t M = uint64_t(1) << t.max_buckets_log2;
+  const uint64_t MB = uint64_t(1) << t.max_link_buckets_log2;
+  const uint64_t MRC = uint64_t(1) << t.max_rc_buckets_log2;
   const uint64_t T = uint64_t(1) << t.tile_log2;
-  const uint64_t bmax = std::min<uint64_t>(M, 2 * P / uint64_t(lt) + 1);
-  const uint64_t rmax = std::min<uint64_t>(M, 2 * P / uint64_t(rt) + 1);
+  const uint64_t bmax = std::min<uint64_t>(MB, 2 * P / uint64_t(lt) + 1);
+  const uint64_t rmax = std::min<uint64_t>(MRC, 2 * P / uint64_t(rt) + 1);
   const uint64_t tilemeta = (P / T + W) * (bmax + 2);
   const uint64_t lbmeta = (std::min<uint64_t>(bmax * W, 2 * P / uint64_t(lt) + W)) * (2 * rmax + 3);
   return size_t(P * 24 + (tilemeta + lbmeta + W) * 4 + 8 * 256);

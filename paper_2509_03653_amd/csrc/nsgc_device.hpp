@@ -133,6 +133,12 @@ __device__ __forceinline__ uint32_t readlane(uint32_t v, int lane) {
   return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), lane));
 }
 
+// The value of `v` held by lane `src` (a per-lane index 0..63), by ds_bpermute.
+__device__ __forceinline__ uint32_t lane_take(uint32_t v, uint32_t src) {
+  return static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(static_cast<int>(src << 2),
+                                                            static_cast<int>(v)));
+}
+
 // Set bits of `m` below the calling lane.
 __device__ __forceinline__ uint32_t rank_below(u64 m) {
   return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));

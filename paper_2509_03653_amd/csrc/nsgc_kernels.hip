@@ -268,18 +268,18 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
 // the bucket-major tile table.
 // ---------------------------------------------------------------------------
 
-size_t lds_part_bytes(uint32_t max_buckets, uint32_t tile_log2) {
-  return align16((max_buckets + 1) * 4) + align16((size_t(1) << tile_log2) * 8) + 256;
+size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2) {
+  return align16((max_link_buckets + 1) * 4) + align16((size_t(1) << tile_log2) * 8) + 256;
 }
 
 template <int PER>
 __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* __restrict__ P,
-                                                          uint32_t max_buckets) {
+                                                          uint32_t max_link_buckets) {
   static_assert(PER % 4 == 0, "PER must be a multiple of 4");
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr uint32_t T = NSGC_BLOCK * PER;
   uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
-  u64* stage = reinterpret_cast<u64*>(smem + align16((max_buckets + 1) * 4));
+  u64* stage = reinterpret_cast<u64*>(smem + align16((max_link_buckets + 1) * 4));
   uint32_t* red = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(stage) + T * 8);
   const uint32_t items = P->itemsA;
   for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
@@ -350,8 +350,13 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* _
 // Wavefront w takes segments w, w + WAVES, w + 2 WAVES, ... of each group of
 // 64 * WAVES segments; its lanes load the descriptions of the wave's (up to
 // 64) segments at once, and the wave walks them in chunks of 64 consecutive
-// elements (lane = offset in the chunk), up to MAXU chunks per round.  There
-// is no LDS staging, scan or per-element segment search, and no barrier
+// elements, up to MAXU chunks per round.  Long segments are walked one at a
+// time (lane = offset in the chunk; a segment's last chunk may be partly
+// idle).  When the segments are short (large windows cut into many buckets
+// and tiles) that would leave most lanes idle, so the wave instead walks the
+// concatenation of its segments: lane l of a chunk at position v takes
+// element v + l, whose segment a 6-step binary search over the lanes'
+// inclusive length prefix finds.  There is no LDS staging and no barrier
 // until the one at the end, so waves proceed independently.  `fn(pos, ok)`
 // receives the round's positions (pos[u] valid when ok[u]; the array length
 // is the round's unroll) with the whole wavefront active; it must not use
@@ -363,8 +368,8 @@ __device__ __forceinline__ u64 readlane64(u64 v, uint32_t k) {
 }
 
 // Rounds over `total` chunks (uniform across the wavefront, not the block):
-// body(integral_constant<int, UU>) with the smallest UU of 4, 2, 1 (at most
-// MAXU) that covers what is left.
+// body(integral_constant<int, UU>) with the smallest UU of 8, 4, 2, 1 (at
+// most MAXU) that covers what is left.
 template <int MAXU, class Body>
 __device__ __forceinline__ void for_chunk_rounds(uint32_t total, Body&& body) {
   static_assert(MAXU == 8 || MAXU == 4 || MAXU == 2 || MAXU == 1, "unroll");
@@ -392,20 +397,54 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
   return uint32_t(__builtin_amdgcn_readfirstlane(int(v)));
 }
 
+// The packed walk is taken when it needs fewer than PACK_NUM / PACK_DEN of
+// the segment-by-segment walk's chunks (its search costs part of a chunk).
+constexpr uint32_t PACK_NUM = 3, PACK_DEN = 4;
+
 template <int MAXU, class SegFn, class BatchFn>
 __device__ __forceinline__ void gather_by_wave(uint32_t nseg, SegFn seg, BatchFn fn) {
   const uint32_t w = uniform(threadIdx.x >> 6), lane = lane_id();
   constexpr uint32_t GROUP = 64u * uint32_t(WAVES);
+  constexpr int PACKU = MAXU < 4 ? MAXU : 4;
   for (uint32_t g0 = 0; g0 < nseg; g0 += GROUP) {
     const uint32_t si = g0 + w + uint32_t(WAVES) * lane;   // this lane's segment
     u64 mybase = 0;
     uint32_t mylen = 0;
     if (si < nseg) seg(si, mybase, mylen);
     const uint32_t nk = uniform(g0 + w < nseg ? min(64u, (nseg - g0 - w + WAVES - 1) / WAVES) : 0u);
-    const uint32_t total = uniform(wave_sum((mylen + 63u) >> 6));   // the wave's chunks
+    const uint32_t chunks = uniform(wave_sum((mylen + 63u) >> 6));   // segment by segment
+    const uint32_t elems = uniform(wave_sum(mylen));
+    const uint32_t packed_chunks = (elems + 63u) >> 6;               // concatenated
+    if (PACK_DEN * packed_chunks < PACK_NUM * chunks) {
+      // Packed walk, in rounds of at most 4 chunks (the search's registers
+      // stay out of the widest round).  Lane l of the chunk at v takes
+      // element v + l of the concatenation; its segment j is the number of
+      // lanes whose inclusive prefix is <= v + l (empty segments skipped).
+      const uint32_t incl = wave_inclusive_scan(mylen);
+      const u64 mb = mybase - (incl - mylen);   // base - exclusive prefix
+      uint32_t v0 = 0;
+      for_chunk_rounds<PACKU>(packed_chunks, [&](auto uc) {
+        constexpr int U = decltype(uc)::value;
+        u64 pos[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t v = v0 + lane;
+          uint32_t j = 0;
+#pragma unroll
+          for (uint32_t st = 32; st > 0; st >>= 1)
+            if (lane_take(incl, j + st - 1) <= v) j += st;
+          pos[u] = ((u64(lane_take(uint32_t(mb >> 32), j)) << 32) | lane_take(uint32_t(mb), j)) + v;
+          ok[u] = v < elems;
+          v0 = uniform(v0 + 64);
+        }
+        fn(pos, ok);
+      });
+      continue;
+    }
     uint32_t k = 0, off = 0;                                          // uniform cursor
     while (k < nk && readlane(mylen, int(k)) == 0) k = uniform(k + 1);
-    for_chunk_rounds<MAXU>(total, [&](auto uc) {
+    for_chunk_rounds<MAXU>(chunks, [&](auto uc) {
       constexpr int U = decltype(uc)::value;
       u64 pos[U];
       bool ok[U];
@@ -456,9 +495,9 @@ __device__ __forceinline__ void gather_by_wave(uint32_t nseg, SegFn seg, BatchFn
 // written in a second.
 // ---------------------------------------------------------------------------
 
-size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_buckets) {
+size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_rc_buckets) {
   const size_t S = size_t(1) << slots_log2;
-  return align16(S * 8) + align16(S * 4) + align16(S * 4) + 2 * align16((max_buckets + 1) * 4) +
+  return align16(S * 8) + align16(S * 4) + align16(S * 4) + 2 * align16((max_rc_buckets + 1) * 4) +
          256;
 }
 
@@ -468,7 +507,7 @@ size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_buckets) {
 // combining code's registers.
 template <bool COMBINE>
 __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_links(
-    nsgc_dev_plan* P, uint32_t max_buckets) {
+    nsgc_dev_plan* P, uint32_t max_rc_buckets) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t S = 1u << P->link_slots_log2;
   unsigned char* p = smem;
@@ -476,8 +515,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
   uint32_t* tc = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
   uint32_t* occ = reinterpret_cast<uint32_t*>(p);      p += align16(S * 4);
   struct { uint32_t* red; } st;                        // reduction scratch (in misc)
-  uint32_t* histR = reinterpret_cast<uint32_t*>(p);    p += align16((max_buckets + 1) * 4);
-  uint32_t* histC = reinterpret_cast<uint32_t*>(p);    p += align16((max_buckets + 1) * 4);
+  uint32_t* histR = reinterpret_cast<uint32_t*>(p);    p += align16((max_rc_buckets + 1) * 4);
+  uint32_t* histC = reinterpret_cast<uint32_t*>(p);    p += align16((max_rc_buckets + 1) * 4);
   uint32_t* misc = reinterpret_cast<uint32_t*>(p);
   // misc: [0] fail flag, [1] special link count, [4] emission base,
   // [5] occupied slots, [7] queue slot, [8..24) reduction scratch
@@ -1067,26 +1106,26 @@ hipError_t launch_small(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t max_buckets,
+hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t max_link_buckets,
                             uint32_t grid, size_t lds, hipStream_t s) {
   switch (tile_log2) {
-    case 11: hipLaunchKernelGGL(k_partition<4>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_buckets); break;
-    case 12: hipLaunchKernelGGL(k_partition<8>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_buckets); break;
-    case 13: hipLaunchKernelGGL(k_partition<16>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_buckets); break;
-    case 14: hipLaunchKernelGGL(k_partition<32>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_buckets); break;
+    case 11: hipLaunchKernelGGL(k_partition<4>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
+    case 12: hipLaunchKernelGGL(k_partition<8>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
+    case 13: hipLaunchKernelGGL(k_partition<16>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
+    case 14: hipLaunchKernelGGL(k_partition<32>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_buckets, uint32_t grid,
+hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_buckets, uint32_t grid,
                         size_t lds, hipStream_t s) {
   if (combine)
     hipLaunchKernelGGL(k_links<true>, dim3(grid), dim3(NSGC_BLOCK), lds, s,
-                       const_cast<nsgc_dev_plan*>(P), max_buckets);
+                       const_cast<nsgc_dev_plan*>(P), max_rc_buckets);
   else
     hipLaunchKernelGGL(k_links<false>, dim3(grid), dim3(NSGC_BLOCK), lds, s,
-                       const_cast<nsgc_dev_plan*>(P), max_buckets);
+                       const_cast<nsgc_dev_plan*>(P), max_rc_buckets);
   return hipGetLastError();
 }
 

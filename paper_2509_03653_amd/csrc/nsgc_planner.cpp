@@ -25,7 +25,8 @@ void default_tune(nsgc_tune* t) {
   t->link_slots_log2 = 12;
   t->rc_slots_log2 = 12;
   t->blocks_per_cu = 3;
-  t->max_buckets_log2 = 10;
+  t->max_link_buckets_log2 = 10;
+  t->max_rc_buckets_log2 = 10;
   t->max_sweeps_log2 = 24;
   t->combine_probes = 0;
   for (int k = 0; k <= 32; ++k) {
@@ -41,7 +42,8 @@ int check_tune(const nsgc_tune& t) {
   if (t.link_slots_log2 < 10 || t.link_slots_log2 > 12) return NSGC_ERR_INVALID_ARG;
   if (t.rc_slots_log2 < 10 || t.rc_slots_log2 > 13) return NSGC_ERR_INVALID_ARG;
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16) return NSGC_ERR_INVALID_ARG;
-  if (t.max_buckets_log2 < 0 || t.max_buckets_log2 > 12) return NSGC_ERR_INVALID_ARG;
+  if (t.max_link_buckets_log2 < 0 || t.max_link_buckets_log2 > 12) return NSGC_ERR_INVALID_ARG;
+  if (t.max_rc_buckets_log2 < 0 || t.max_rc_buckets_log2 > 12) return NSGC_ERR_INVALID_ARG;
   if (t.max_sweeps_log2 < 0 || t.max_sweeps_log2 > 24) return NSGC_ERR_INVALID_ARG;
   if (t.combine_probes < 0 || t.combine_probes > 64) return NSGC_ERR_INVALID_ARG;
   for (int k = 0; k <= 32; ++k) {
@@ -96,15 +98,15 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
     int cls = 0;
     while (cls < 32 && (uint64_t(1) << (cls + 1)) <= n) ++cls;
     const nsgc_tune_class& tc = tune.cls[cls];
-    const int cap = tune.max_buckets_log2;
+    const int capB = tune.max_link_buckets_log2, capRC = tune.max_rc_buckets_log2;
     nsgc_win_desc d;
     std::memset(&d, 0, sizeof d);
     d.in_begin = offsets[w];
     d.n = uint32_t(n);
     d.out_index = uint32_t(w);
-    d.logB = uint8_t(std::min(ceil_log2((n + uint64_t(tc.link_target) - 1) / uint64_t(tc.link_target)), cap));
-    d.logR = uint8_t(std::min(ceil_log2((n + uint64_t(tc.row_target) - 1) / uint64_t(tc.row_target)), cap));
-    d.logC = uint8_t(std::min(ceil_log2((n + uint64_t(tc.col_target) - 1) / uint64_t(tc.col_target)), cap));
+    d.logB = uint8_t(std::min(ceil_log2((n + uint64_t(tc.link_target) - 1) / uint64_t(tc.link_target)), capB));
+    d.logR = uint8_t(std::min(ceil_log2((n + uint64_t(tc.row_target) - 1) / uint64_t(tc.row_target)), capRC));
+    d.logC = uint8_t(std::min(ceil_log2((n + uint64_t(tc.col_target) - 1) / uint64_t(tc.col_target)), capRC));
     d.ntiles = uint32_t((n + tile - 1) / tile);
     d.counter = uint32_t(p->win.size());
     d.ws = p->ws_elems;
@@ -182,10 +184,12 @@ size_t plan_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune& t) 
   }
   // A bucket count is the power of two at or above ceil(n_w / target) < n_w /
   // target + 1, so B_w < 2 n_w / lt + 2 and R_w + C_w < 4 n_w / rt + 4; each
-  // count is also at most 2^max_buckets_log2 per window.
-  const uint64_t cap = uint64_t(1) << t.max_buckets_log2;
-  const uint64_t nb = std::min<uint64_t>(2 * P / lt + 2 * W, W * cap);
-  const uint64_t nc = std::min<uint64_t>(4 * P / rt + 4 * W, 2 * W * cap);
+  // count is also at most its cap (2^max_link_buckets_log2, 2^max_rc_buckets_log2)
+  // per window.
+  const uint64_t capB = uint64_t(1) << t.max_link_buckets_log2;
+  const uint64_t capRC = uint64_t(1) << t.max_rc_buckets_log2;
+  const uint64_t nb = std::min<uint64_t>(2 * P / lt + 2 * W, W * capB);
+  const uint64_t nc = std::min<uint64_t>(4 * P / rt + 4 * W, 2 * W * capRC);
   return plan_offsets(size_t(W), size_t(W), size_t(nb), size_t(nc)).total + 1024;
 }
 

@@ -78,7 +78,8 @@ def test_tune_roundtrip_and_validation():
     assert d["max_sweeps_log2"] == 24
     for k, v in (("tile_log2", 9), ("tile_log2", 15), ("link_slots_log2", 13),
                  ("rc_slots_log2", 14), ("small_max", 2049), ("blocks_per_cu", 0),
-                 ("max_buckets_log2", 13), ("max_sweeps_log2", 25), ("max_sweeps_log2", -1),
+                 ("max_link_buckets_log2", 13), ("max_rc_buckets_log2", 13),
+                 ("max_link_buckets_log2", -1), ("max_sweeps_log2", 25), ("max_sweeps_log2", -1),
                  ("combine_probes", -1), ("combine_probes", 65)):
         with pytest.raises(nsgc.NsgcError):
             nsgc.set_tune(nsgc.Tune.from_dict(dict(d, **{k: v})))
@@ -112,7 +113,7 @@ def test_plan_tiers_and_cutover():
         assert p["tiles"][i] == -(-sizes[i] // tile)
         cls = int(np.floor(np.log2(sizes[i])))
         lt = t.cls[cls].link_target
-        want = min(int(np.ceil(np.log2(max(1, -(-sizes[i] // lt))))), t.max_buckets_log2)
+        want = min(int(np.ceil(np.log2(max(1, -(-sizes[i] // lt))))), t.max_link_buckets_log2)
         assert p["log2_link_buckets"][i] == want
     assert p["workspace_bytes"] >= 24 * (sum(sizes[3:]))
 

@@ -53,7 +53,8 @@ def test_every_point_of_the_space_is_a_valid_tuning():
 def test_search_finds_the_separable_optimum():
     # cost model with a known optimum; coordinate descent must reach it
     opt = {"blocks_per_cu": 3, "link_slots_log2": 11, "rc_slots_log2": 13, "tile_log2": 14,
-           "small_max": 512, "link_scale": 2.0, "rc_scale": 0.5, "combine_probes": 64}
+           "small_max": 512, "link_scale": 2.0, "max_link_buckets_log2": 11, "rc_scale": 0.5,
+           "combine_probes": 64}
     assert set(opt) == {k for k, _ in at.SPACE}
     calls = []
 

@@ -128,6 +128,19 @@ def test_workloads_scaled_down(maker):
     check(src, dst, wl.offsets, maker, forms=("batched", "plain"))
 
 
+@pytest.mark.parametrize("link_cap", [10, 12])
+def test_large_window_short_segments(link_cap):
+    # 2^21 packets cut into 128 tiles and 1024 (or more) link buckets leave
+    # ~16 keys per (tile, bucket) segment and a few entries per (link bucket,
+    # row bucket) segment: the gathers walk their segments concatenated
+    wl = synth.uneven_batch(seed=6, num_windows=3, lo_log2=20, hi_log2=21)
+    src, dst = wl.generate()
+    base = nsgc.default_tune().to_dict()
+    base.update(max_link_buckets_log2=link_cap)
+    nsgc.set_tune(nsgc.Tune.from_dict(base))
+    check(src, dst, wl.offsets, f"large windows link cap 2^{link_cap}")
+
+
 TUNES = {
     "tiny_tables_forced_sweeps": dict(link_slots_log2=10, rc_slots_log2=10,
                                       cls=[[65536, 65536, 65536]] * 33),
@@ -135,8 +148,9 @@ TUNES = {
     "small_tier_max": dict(small_max=2048),
     "tile_2k": dict(tile_log2=11),
     "tile_16k": dict(tile_log2=14),
-    "one_bucket": dict(max_buckets_log2=0),
-    "many_buckets": dict(cls=[[64, 64, 64]] * 33, max_buckets_log2=12),
+    "one_bucket": dict(max_link_buckets_log2=0, max_rc_buckets_log2=0),
+    "many_buckets": dict(cls=[[64, 64, 64]] * 33, max_link_buckets_log2=12,
+                         max_rc_buckets_log2=12),
     "big_tables": dict(link_slots_log2=12, rc_slots_log2=13, blocks_per_cu=1),
     # per-id combining in phase B, and its fallback (gives up almost always)
     "combine": dict(combine_probes=64),
@@ -204,7 +218,8 @@ def test_graph_plan_holds_many_items_per_window():
     # graph is created, must hold their per-item tables
     import torch
     base = nsgc.default_tune().to_dict()
-    base.update(cls=[[64, 64, 64]] * 33, max_buckets_log2=12, small_max=0)
+    base.update(cls=[[64, 64, 64]] * 33, max_link_buckets_log2=12, max_rc_buckets_log2=12,
+                small_max=0)
     nsgc.set_tune(nsgc.Tune.from_dict(base))
     g = nsgc.Graph(1 << 20, 4)
     try:
@@ -252,8 +267,9 @@ def test_heavy_links_split_entries():
     s2 = np.concatenate([src, src[:1000], src[: n // 2]])
     d2 = np.concatenate([dst, dst[:1000], dst[: n // 2]])
     check(s2, d2, off, "heavy links", forms=("batched", "plain"))
-    for extra in (dict(max_buckets_log2=0), dict(combine_probes=1), dict(combine_probes=64),
-                  dict(link_slots_log2=10, max_buckets_log2=0)):   # overflow sweeps
+    one = dict(max_link_buckets_log2=0, max_rc_buckets_log2=0)
+    for extra in (one, dict(combine_probes=1), dict(combine_probes=64),
+                  dict(link_slots_log2=10, **one)):   # overflow sweeps
         base = nsgc.default_tune().to_dict()
         base.update(extra)
         nsgc.set_tune(nsgc.Tune.from_dict(base))
@@ -282,7 +298,8 @@ def test_abandoned_bucket_is_reported_not_hung():
     want = oracle.window_stats(src, dst, off)
     base = nsgc.default_tune().to_dict()
     base.update(link_slots_log2=12, rc_slots_log2=10, max_sweeps_log2=0, small_max=1024,
-                cls=[[1 << 20, 1 << 20, 1 << 20]] * 33, max_buckets_log2=0)
+                cls=[[1 << 20, 1 << 20, 1 << 20]] * 33,
+                max_link_buckets_log2=0, max_rc_buckets_log2=0)
     nsgc.set_tune(nsgc.Tune.from_dict(base))
     for form in ("batched", "plain"):
         say(f"[gpu] abandoned buckets form={form}")
