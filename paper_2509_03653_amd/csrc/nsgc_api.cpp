@@ -23,6 +23,7 @@ hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t
                             uint32_t grid, size_t lds, hipStream_t s);
 hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_buckets, uint32_t grid,
                         size_t lds, hipStream_t s);
+hipError_t launch_order(const nsgc_dev_plan* P, hipStream_t s);
 hipError_t launch_rowcol(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
 size_t lds_small_bytes(uint32_t slots_log2);
 size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2);
@@ -241,6 +242,7 @@ int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch
     NSGC_HIP(launch_links(dplan, L.combine, L.max_rc_buckets, grid(hp.itemsB, L.grid_link),
                           L.lds_link, s));
   NSGC_HIP(mark(3));
+  if (part) NSGC_HIP(launch_order(dplan, s));
   if (part) NSGC_HIP(launch_rowcol(dplan, grid(hp.itemsC, L.grid_rc), L.lds_rc, s));
   NSGC_HIP(mark(4));
   return NSGC_OK;
@@ -307,7 +309,9 @@ size_t workspace_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune
   const uint64_t rmax = std::min<uint64_t>(MRC, 2 * P / uint64_t(rt) + 1);
   const uint64_t tilemeta = (P / T + W) * (bmax + 2);
   const uint64_t lbmeta = (std::min<uint64_t>(bmax * W, 2 * P / uint64_t(lt) + W)) * (2 * rmax + 3);
-  return size_t(P * 24 + (tilemeta + lbmeta + W) * 4 + 8 * 256);
+  // phase-C items: R_w + C_w < 4 n_w / rt + 4 per window, at most 2 * MRC
+  const uint64_t items = std::min<uint64_t>(4 * P / uint64_t(rt) + 4 * W, 2 * W * MRC);
+  return size_t(P * 24 + (tilemeta + lbmeta + 2 * items) * 4 + 8 * 256);
 }
 
 

@@ -386,38 +386,75 @@ __device__ __forceinline__ uint32_t owner_of_wave(const NSGC_GLOBAL uint32_t* pr
   return lo;
 }
 
-// Dynamic work queue: workgroups take items in order from an atomic counter,
-// so uneven items (heavy buckets, windows of very different sizes) spread over
-// the grid.  The next item is requested while the current one is processed.
+// Dynamic work queue, so that uneven items (heavy buckets, windows of very
+// different sizes) spread over the grid.  Device-scope atomics on one
+// address are serialised (tens of ns each), which a queue of thousands of
+// items per launch would pay on every item, so: workgroup b takes item b
+// first without any atomic, and the remaining items are dealt round-robin
+// over K = min(classes, grid) classes (classes <= NSGC_QCLASSES), each with
+// its own counter on its own cache line; workgroup b takes the items of
+// class b mod K (every class has workgroups).  The next item is requested while the current one
+// is processed.
+//
+// Queue positions map to items through `map` (a permutation of the items;
+// null for the identity).  A kernel that maps may call resolve() part-way
+// through an item, so that the next item's map entry is loaded while the
+// current item finishes instead of when the next one starts.
 struct ItemQueue {
-  NSGC_GLOBAL uint32_t* counter;
-  uint32_t* slot;        // LDS word that broadcasts the item to the workgroup
-  uint32_t pending;      // thread 0: prefetched next item
+  NSGC_GLOBAL uint32_t* counter;  // this workgroup's class counter
+  uint32_t* slot;                 // LDS word that broadcasts the item to the workgroup
+  const NSGC_GLOBAL uint32_t* map;
+  uint32_t base, step;            // dynamic positions of the class: base + step * ticket
+  uint32_t pending;               // thread 0: prefetched next position
+  uint32_t pending_item;          // thread 0: its item, once resolved
+  bool resolved;
+
+  __device__ ItemQueue(NSGC_GLOBAL uint32_t* counters, uint32_t* lds_slot, uint32_t classes,
+                       const NSGC_GLOBAL uint32_t* item_map = nullptr)
+      : slot(lds_slot), map(item_map), pending(0), pending_item(0), resolved(false) {
+    step = min(min(classes, uint32_t(NSGC_QCLASSES)), gridDim.x);
+    const uint32_t c = blockIdx.x % step;
+    counter = counters + c * NSGC_QSTRIDE;
+    base = gridDim.x + c;          // after the grid's static first positions
+  }
 
   __device__ __forceinline__ uint32_t take() {
-    return __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t t =
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return base + step * t;
+  }
+  __device__ __forceinline__ uint32_t item_at(uint32_t pos, uint32_t items) const {
+    return pos < items ? (map ? map[pos] : pos) : items;
   }
   __device__ __forceinline__ uint32_t first(uint32_t items) {
     if (threadIdx.x == 0) {
-      const uint32_t v = take();
-      slot[0] = v;
+      const uint32_t v = blockIdx.x;
+      slot[0] = item_at(v, items);
       pending = v < items ? take() : items;
+      resolved = false;
     }
     __syncthreads();
-    const uint32_t v = slot[0];
+    const uint32_t it = slot[0];
     __syncthreads();
-    return v;
+    return it;
+  }
+  __device__ __forceinline__ void resolve(uint32_t items) {
+    if (threadIdx.x == 0 && !resolved) {
+      pending_item = item_at(pending, items);
+      resolved = true;
+    }
   }
   __device__ __forceinline__ uint32_t next(uint32_t items) {
     if (threadIdx.x == 0) {
       const uint32_t v = pending;
-      slot[0] = v;
+      slot[0] = resolved ? pending_item : item_at(v, items);
+      resolved = false;
       pending = v < items ? take() : items;
     }
     __syncthreads();
-    const uint32_t v = slot[0];
+    const uint32_t it = slot[0];
     __syncthreads();
-    return v;
+    return it;
   }
 };
 

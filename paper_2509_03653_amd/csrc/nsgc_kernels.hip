@@ -77,6 +77,9 @@ constexpr u64 NSGC_INVALID_BIT = 1ull << 63;
 // Phase B holds 64-bit keys; four elements per thread keep it within 128
 // VGPRs, i.e. two 512-thread workgroups per compute unit.
 constexpr int LINK_MAXU = 4;
+// Work-queue classes of phase B (at most NSGC_QCLASSES): one measured best;
+// its prefetched atomic hides behind the item.
+constexpr uint32_t LINK_QCLASSES = 1;
 constexpr int RC_MAXU = 8;
 // Links a thread holds while phase B combines them per source and
 // destination: the link table has at most LK * NSGC_BLOCK slots.
@@ -142,7 +145,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
   uint32_t* red = misc + 8;
 
   const uint32_t items = P->num_small;
-  ItemQueue q{gptr(&P->queue[0]), misc + 7, 0};
+  ItemQueue q(gptr(&P->queue[0][0]), misc + 7, NSGC_QCLASSES);
   for (uint32_t item = q.first(items); item < items; item = q.next(items)) {
     const nsgc_small_desc D = gload(P->small + item);
     for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
@@ -281,6 +284,13 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* _
   uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
   u64* stage = reinterpret_cast<u64*>(smem + align16((max_link_buckets + 1) * 4));
   uint32_t* red = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(stage) + T * 8);
+  // clear the phase-C item sizes that phase B accumulates for the ordering
+  if (P->order_items) {
+    NSGC_GLOBAL uint32_t* sz = gptr(P->rcsize);
+    const uint32_t nc = P->itemsC;
+    for (uint32_t i = blockIdx.x * NSGC_BLOCK + threadIdx.x; i < nc; i += gridDim.x * NSGC_BLOCK)
+      sz[i] = 0;
+  }
   const uint32_t items = P->itemsA;
   for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
     const uint32_t wi = owner_of_wave(gptr(P->prefA), P->num_part, item);
@@ -531,7 +541,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 
   const uint32_t T = 1u << P->tile_log2;
   const uint32_t items = P->itemsB;
-  ItemQueue q{gptr(&P->queue[1]), misc + 7, 0};
+  ItemQueue q(gptr(&P->queue[1][0]), misc + 7, LINK_QCLASSES);
   for (uint32_t item = q.first(items); item < items; item = q.next(items)) {
     const uint32_t it = uniform(item);
     const uint32_t wi = sload(P->itemwinB + it);
@@ -814,6 +824,15 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
       __syncthreads();
     };
     auto publish = [&]() {
+      // the counts go to the phase-C items' sizes (a scheduling hint: large
+      // items are started first) before the scan turns them into starts
+      if (P->order_items) {
+        NSGC_GLOBAL uint32_t* sz = gptr(P->rcsize) + sload(P->prefC + wi);
+        for (uint32_t i = threadIdx.x; i < R + C; i += NSGC_BLOCK) {
+          const uint32_t v = i < R ? histR[i] : histC[i - R];
+          if (v) __hip_atomic_fetch_add(sz + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
       block_exclusive_scan2(histR, R, histC, C, st.red);
       for (uint32_t i = threadIdx.x; i <= R; i += NSGC_BLOCK) rec[B + u64(i) * B + b] = histR[i];
       for (uint32_t i = threadIdx.x; i <= C; i += NSGC_BLOCK)
@@ -919,6 +938,81 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 }
 
 // ---------------------------------------------------------------------------
+// Order of the phase-C items: those with at least four times the mean entry
+// count first, then the rest, each group in item order.  A row bucket that
+// holds a dominant source takes several times longer than the others; the
+// work queue hands positions out in order, so such items start at once
+// instead of possibly last, where they would set the kernel's end.  This
+// matters when the grid gets a few items per workgroup, so the plan asks for
+// it only for batches of at most NSGC_ORDER_MAX items (else the kernel
+// returns and phase C takes the items in their own order).  One workgroup;
+// each thread holds up to NSGC_ORDER_MAX / NSGC_BLOCK consecutive sizes in
+// registers.  The result is a permutation of the items, which is all that
+// the correctness of phase C depends on.
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t ORDER_PER = NSGC_ORDER_MAX / NSGC_BLOCK;
+
+__global__ __launch_bounds__(NSGC_BLOCK) void k_order(nsgc_dev_plan* P) {
+  __shared__ u64 red[WAVES];
+  __shared__ uint32_t wsum[2 * WAVES];
+  const uint32_t n = P->itemsC;
+  if (!P->order_items || n == 0) return;
+  const NSGC_GLOBAL uint32_t* sz = gptr(P->rcsize);
+  NSGC_GLOBAL uint32_t* order = gptr(P->order);
+  const uint32_t per = (n + NSGC_BLOCK - 1) / NSGC_BLOCK;   // <= ORDER_PER
+  const uint32_t beg = threadIdx.x * per;
+  uint32_t v[ORDER_PER];
+  u64 tot = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < ORDER_PER; ++k) {
+    const uint32_t i = beg + k;
+    v[k] = (k < per && i < n) ? sz[i] : 0u;
+    tot += v[k];
+  }
+  // mean over all items -> threshold
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+  const uint32_t w = threadIdx.x >> 6;
+  if (lane_id() == 0) red[w] = tot;
+  __syncthreads();
+  tot = 0;
+#pragma unroll
+  for (int k = 0; k < WAVES; ++k) tot += red[k];
+  const u64 thr = max(4 * tot / n, u64(64));
+  uint32_t hv = 0, nv = 0;   // this thread's large and other items
+#pragma unroll
+  for (uint32_t k = 0; k < ORDER_PER; ++k) {
+    if (k < per && beg + k < n) {
+      if (v[k] >= thr) ++hv; else ++nv;
+    }
+  }
+  // exclusive block scan of (hv, nv)
+  const uint32_t ih = wave_inclusive_scan(hv), in = wave_inclusive_scan(nv);
+  if (lane_id() == 63) {
+    wsum[w] = ih;
+    wsum[WAVES + w] = in;
+  }
+  __syncthreads();
+  uint32_t hb = 0, nb = 0, H = 0;
+#pragma unroll
+  for (int k = 0; k < WAVES; ++k) {
+    if (uint32_t(k) < w) {
+      hb += wsum[k];
+      nb += wsum[WAVES + k];
+    }
+    H += wsum[k];
+  }
+  hb += ih - hv;
+  nb += H + in - nv;
+#pragma unroll
+  for (uint32_t k = 0; k < ORDER_PER; ++k) {
+    const uint32_t i = beg + k;
+    if (k < per && i < n) order[v[k] >= thr ? hb++ : nb++] = i;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Phase C: aggregation of one row bucket (or column bucket).
 //
 // Gathers the bucket's (id, packets, links) entries -- at most one per id and
@@ -954,7 +1048,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
   }
 
   const uint32_t items = P->itemsC;
-  ItemQueue q{gptr(&P->queue[2]), misc + 7, 0};
+  ItemQueue q(gptr(&P->queue[2][0]), misc + 7, NSGC_QCLASSES,
+              P->order_items ? gptr(P->order) : nullptr);
   for (uint32_t item = q.first(items); item < items; item = q.next(items)) {
     const uint32_t it = uniform(item);
     const uint32_t wi = sload(P->itemwinC + it);
@@ -1083,6 +1178,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
       }
       if (!failed) break;
     }
+    q.resolve(items);
     block_sum_max2_to0(n, mp, ml, st.red);   // thread 0 holds the bucket's totals
     if (threadIdx.x == 0) {
       NSGC_GLOBAL u64* o = gptr(P->out) + u64(W.out_index) * 9 + (is_row ? 3 : 6);
@@ -1126,6 +1222,11 @@ hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_bu
   else
     hipLaunchKernelGGL(k_links<false>, dim3(grid), dim3(NSGC_BLOCK), lds, s,
                        const_cast<nsgc_dev_plan*>(P), max_rc_buckets);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const nsgc_dev_plan* P, hipStream_t s) {
+  hipLaunchKernelGGL(k_order, dim3(1), dim3(NSGC_BLOCK), 0, s, const_cast<nsgc_dev_plan*>(P));
   return hipGetLastError();
 }
 

@@ -39,6 +39,11 @@
 // the packet field holds is emitted as several entries that sum to it (phase C
 // adds them up).  Since links <= packets no triple needs more entries than it
 // has packets, so an emission region of one slot per packet suffices.
+// Work-queue counters per kernel, one per 128-byte line (see ItemQueue).
+#define NSGC_QCLASSES 8
+#define NSGC_QSTRIDE 32
+// Batches of at most this many phase-C items have them ordered large first.
+#define NSGC_ORDER_MAX 16384
 #define NSGC_ENT_PACKET_BITS 19
 #define NSGC_ENT_LINK_BITS 13
 
@@ -83,7 +88,9 @@ struct nsgc_dev_plan {          // header of the device plan buffer
   unsigned long long* emit_col; // column entries (dst, links, packets)
   uint32_t* tilemeta;
   uint32_t* lbmeta;
-  uint32_t* counters;
+  uint32_t* rcsize;             // [itemsC] entries per phase-C item (cleared by phase A,
+                                //   summed by phase B)
+  uint32_t* order;              // [itemsC] phase-C items, large ones first
   const nsgc_small_desc* small;
   const nsgc_win_desc* win;
   const uint32_t* prefA;        // [num_part + 1] first phase-A item of each window
@@ -100,10 +107,10 @@ struct nsgc_dev_plan {          // header of the device plan buffer
   uint32_t small_slots_log2;
   uint32_t max_sweeps_log2;     // overflow sweeps allowed before a bucket is abandoned
   uint32_t combine_probes;      // 0: per-link emission; else probe limit of the combining table
-  uint32_t pad;
-  // Work-queue counters of the small, B and C kernels (workgroups take items
-  // in order with an atomic increment).  Uploaded as zero with every plan.
-  uint32_t queue[4];
+  uint32_t order_items;         // 1: phase C takes its items in the order of `order`
+  // Work-queue counters of the small, B and C kernels.  Uploaded as zero
+  // with every plan.
+  uint32_t queue[3][NSGC_QCLASSES * NSGC_QSTRIDE];
 };
 
 #endif  // NSGC_PLAN_H_

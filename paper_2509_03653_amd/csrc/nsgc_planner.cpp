@@ -146,7 +146,8 @@ WsLayout HostPlan::layout() const {
   L.emit_col = o;  o = align_up(o + e, 256);
   L.tilemeta = o;  o = align_up(o + size_t(tilemeta_words) * 4, 256);
   L.lbmeta = o;    o = align_up(o + size_t(lbmeta_words) * 4, 256);
-  L.counters = o;  o = align_up(o + win.size() * 4, 256);
+  L.rcsize = o;    o = align_up(o + size_t(itemsC) * 4, 256);
+  L.order = o;     o = align_up(o + size_t(itemsC) * 4, 256);
   L.total = std::max<size_t>(o, 256);
   return L;
 }
@@ -209,7 +210,8 @@ void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const ui
   h.emit_col = reinterpret_cast<unsigned long long*>(dev_ws + L.emit_col);
   h.tilemeta = reinterpret_cast<uint32_t*>(dev_ws + L.tilemeta);
   h.lbmeta = reinterpret_cast<uint32_t*>(dev_ws + L.lbmeta);
-  h.counters = reinterpret_cast<uint32_t*>(dev_ws + L.counters);
+  h.rcsize = reinterpret_cast<uint32_t*>(dev_ws + L.rcsize);
+  h.order = reinterpret_cast<uint32_t*>(dev_ws + L.order);
   h.small = reinterpret_cast<const nsgc_small_desc*>(dev_plan + o.small);
   h.win = reinterpret_cast<const nsgc_win_desc*>(dev_plan + o.win);
   h.prefA = reinterpret_cast<const uint32_t*>(dev_plan + o.prefA);
@@ -228,6 +230,7 @@ void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const ui
   h.small_slots_log2 = small_slots_log2;
   h.max_sweeps_log2 = max_sweeps_log2;
   h.combine_probes = combine_probes;
+  h.order_items = itemsC <= NSGC_ORDER_MAX ? 1u : 0u;
   std::memcpy(base, &h, sizeof h);
   if (!small.empty()) std::memcpy(base + o.small, small.data(), small.size() * sizeof(nsgc_small_desc));
   if (!win.empty()) std::memcpy(base + o.win, win.data(), win.size() * sizeof(nsgc_win_desc));

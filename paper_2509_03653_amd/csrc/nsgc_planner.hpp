@@ -15,7 +15,7 @@ namespace nsgc {
 
 // Workspace regions of one batch, as byte offsets from the workspace base.
 struct WsLayout {
-  size_t keys = 0, emit_row = 0, emit_col = 0, tilemeta = 0, lbmeta = 0, counters = 0;
+  size_t keys = 0, emit_row = 0, emit_col = 0, tilemeta = 0, lbmeta = 0, rcsize = 0, order = 0;
   size_t total = 0;
 };
 
