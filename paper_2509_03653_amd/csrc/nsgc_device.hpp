@@ -400,6 +400,12 @@ __device__ __forceinline__ uint32_t owner_of_wave(const NSGC_GLOBAL uint32_t* pr
 // null for the identity).  A kernel that maps may call resolve() part-way
 // through an item, so that the next item's map entry is loaded while the
 // current item finishes instead of when the next one starts.
+//
+// Loop shape (one barrier per item for the queue, shared with the item's
+// last one; the item body must contain a barrier before stage_next):
+//   for (item = q.first(items); item < items; item = q.read()) {
+//     ...;  q.stage_next(items);  __syncthreads();
+//   }
 struct ItemQueue {
   NSGC_GLOBAL uint32_t* counter;  // this workgroup's class counter
   uint32_t* slot;                 // LDS word that broadcasts the item to the workgroup
@@ -434,9 +440,7 @@ struct ItemQueue {
       resolved = false;
     }
     __syncthreads();
-    const uint32_t it = slot[0];
-    __syncthreads();
-    return it;
+    return slot[0];
   }
   __device__ __forceinline__ void resolve(uint32_t items) {
     if (threadIdx.x == 0 && !resolved) {
@@ -444,18 +448,16 @@ struct ItemQueue {
       resolved = true;
     }
   }
-  __device__ __forceinline__ uint32_t next(uint32_t items) {
+  // Thread 0 publishes the next item; visible after the caller's barrier.
+  __device__ __forceinline__ void stage_next(uint32_t items) {
     if (threadIdx.x == 0) {
       const uint32_t v = pending;
       slot[0] = resolved ? pending_item : item_at(v, items);
       resolved = false;
       pending = v < items ? take() : items;
     }
-    __syncthreads();
-    const uint32_t it = slot[0];
-    __syncthreads();
-    return it;
   }
+  __device__ __forceinline__ uint32_t read() const { return slot[0]; }
 };
 
 // ---- LDS open-addressing tables (linear probing) --------------------------

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
 
   const uint32_t items = P->num_small;
   ItemQueue q(gptr(&P->queue[0][0]), misc + 7, NSGC_QCLASSES);
-  for (uint32_t item = q.first(items); item < items; item = q.next(items)) {
+  for (uint32_t item = q.first(items); item < items; item = q.read()) {
     const nsgc_small_desc D = gload(P->small + item);
     for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
       lk[i] = EMPTY64;
@@ -257,6 +257,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
       o[3] = bad ? ~0ull : nr; o[4] = bad ? ~0ull : mr; o[5] = bad ? ~0ull : mf;
       o[6] = bad ? ~0ull : nc; o[7] = bad ? ~0ull : mc; o[8] = bad ? ~0ull : mg;
     }
+    q.stage_next(items);
     __syncthreads();
   }
 }
@@ -542,7 +543,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
   const uint32_t T = 1u << P->tile_log2;
   const uint32_t items = P->itemsB;
   ItemQueue q(gptr(&P->queue[1][0]), misc + 7, LINK_QCLASSES);
-  for (uint32_t item = q.first(items); item < items; item = q.next(items)) {
+  for (uint32_t item = q.first(items); item < items; item = q.read()) {
     const uint32_t it = uniform(item);
     const uint32_t wi = sload(P->itemwinB + it);
     const nsgc_win_desc W = sload_words(P->win + wi);
@@ -656,6 +657,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
         lds_add(&histC[top32(col_hash(EMPTY32), W.logC)], parts);
       }
     };
+    // Emission also empties the table (each listed slot once); the list
+    // length is cleared after its final barrier.
     auto emit = [&]() {
       const uint32_t base = misc[4];
       NSGC_GLOBAL u64* er = gptr(P->emit_row) + W.ws + base;
@@ -673,6 +676,10 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
           const uint32_t s = ok[u] ? occ[i] : 0u;
           key[u] = ok[u] ? tk[s] : 0ull;
           cnt[u] = ok[u] ? tc[s] : 0u;
+          if (ok[u]) {   // last use of the slot: empty it on the way
+            tk[s] = EMPTY64;
+            tc[s] = 0;
+          }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -865,7 +872,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
           if (misc[0]) { failed = true; reset(); break; }
           if (pass == 1) {
             emit();
-            reset();
+            if (threadIdx.x == 0) misc[5] = 0;   // ordered by the next build's barrier
             continue;
           }
           const uint32_t n = misc[5];
@@ -889,7 +896,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
             publish();
             __syncthreads();
             emit();
-            reset();
+            if (threadIdx.x == 0) misc[5] = 0;   // ordered by the reduction's barriers
           } else if (COMBINE && logS == 0) {
             // the only sweep: combine per source and per destination, emit
             u64 lkey[LK];
@@ -933,6 +940,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
       stat_add(o + 1, nlinks);
       stat_max(o + 2, mx);
     }
+    q.stage_next(items);
     __syncthreads();
   }
 }
@@ -1050,7 +1058,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
   const uint32_t items = P->itemsC;
   ItemQueue q(gptr(&P->queue[2][0]), misc + 7, NSGC_QCLASSES,
               P->order_items ? gptr(P->order) : nullptr);
-  for (uint32_t item = q.first(items); item < items; item = q.next(items)) {
+  for (uint32_t item = q.first(items); item < items; item = q.read()) {
     const uint32_t it = uniform(item);
     const uint32_t wi = sload(P->itemwinC + it);
     const nsgc_win_desc W = sload_words(P->win + wi);
@@ -1189,6 +1197,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
       stat_max(o + 1, mp);
       stat_max(o + 2, ml);
     }
+    q.stage_next(items);
     __syncthreads();
   }
 }
