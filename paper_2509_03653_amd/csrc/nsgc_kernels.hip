@@ -946,77 +946,54 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 }
 
 // ---------------------------------------------------------------------------
-// Order of the phase-C items: those with at least four times the mean entry
-// count first, then the rest, each group in item order.  A row bucket that
-// holds a dominant source takes several times longer than the others; the
-// work queue hands positions out in order, so such items start at once
-// instead of possibly last, where they would set the kernel's end.  This
-// matters when the grid gets a few items per workgroup, so the plan asks for
-// it only for batches of at most NSGC_ORDER_MAX items (else the kernel
-// returns and phase C takes the items in their own order).  One workgroup;
-// each thread holds up to NSGC_ORDER_MAX / NSGC_BLOCK consecutive sizes in
-// registers.  The result is a permutation of the items, which is all that
-// the correctness of phase C depends on.
+// Order of the phase-C items, largest first (approximately: by the binary
+// order of magnitude of the entry count, a counting sort over 33 classes).
+// A row bucket that holds a dominant source takes several times longer than
+// the others; the work queue hands positions out in order, so large items
+// start at once instead of possibly last, where they would set the kernel's
+// end.  This matters when the grid gets a few items per workgroup, so the
+// plan asks for it only for batches of at most NSGC_ORDER_MAX items (else
+// the kernel returns and phase C takes the items in their own order).  One
+// workgroup; each thread holds up to NSGC_ORDER_MAX / NSGC_BLOCK
+// consecutive sizes in registers.  The result is a permutation of the items,
+// which is all that the correctness of phase C depends on.
 // ---------------------------------------------------------------------------
 
 constexpr uint32_t ORDER_PER = NSGC_ORDER_MAX / NSGC_BLOCK;
+constexpr uint32_t ORDER_CLASSES = 33;   // 0 for empty items, else 1 + floor(log2(size))
 
 __global__ __launch_bounds__(NSGC_BLOCK) void k_order(nsgc_dev_plan* P) {
-  __shared__ u64 red[WAVES];
-  __shared__ uint32_t wsum[2 * WAVES];
+  __shared__ uint32_t cursor[ORDER_CLASSES];
   const uint32_t n = P->itemsC;
   if (!P->order_items || n == 0) return;
   const NSGC_GLOBAL uint32_t* sz = gptr(P->rcsize);
   NSGC_GLOBAL uint32_t* order = gptr(P->order);
+  if (threadIdx.x < ORDER_CLASSES) cursor[threadIdx.x] = 0;
+  __syncthreads();
   const uint32_t per = (n + NSGC_BLOCK - 1) / NSGC_BLOCK;   // <= ORDER_PER
   const uint32_t beg = threadIdx.x * per;
-  uint32_t v[ORDER_PER];
-  u64 tot = 0;
+  uint32_t cls[ORDER_PER];
 #pragma unroll
   for (uint32_t k = 0; k < ORDER_PER; ++k) {
     const uint32_t i = beg + k;
-    v[k] = (k < per && i < n) ? sz[i] : 0u;
-    tot += v[k];
-  }
-  // mean over all items -> threshold
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
-  const uint32_t w = threadIdx.x >> 6;
-  if (lane_id() == 0) red[w] = tot;
-  __syncthreads();
-  tot = 0;
-#pragma unroll
-  for (int k = 0; k < WAVES; ++k) tot += red[k];
-  const u64 thr = max(4 * tot / n, u64(64));
-  uint32_t hv = 0, nv = 0;   // this thread's large and other items
-#pragma unroll
-  for (uint32_t k = 0; k < ORDER_PER; ++k) {
-    if (k < per && beg + k < n) {
-      if (v[k] >= thr) ++hv; else ++nv;
-    }
-  }
-  // exclusive block scan of (hv, nv)
-  const uint32_t ih = wave_inclusive_scan(hv), in = wave_inclusive_scan(nv);
-  if (lane_id() == 63) {
-    wsum[w] = ih;
-    wsum[WAVES + w] = in;
+    const uint32_t v = (k < per && i < n) ? sz[i] : 0u;
+    cls[k] = v ? 32u - uint32_t(__builtin_clz(v)) : 0u;
+    if (k < per && i < n) lds_add(&cursor[cls[k]], 1);
   }
   __syncthreads();
-  uint32_t hb = 0, nb = 0, H = 0;
-#pragma unroll
-  for (int k = 0; k < WAVES; ++k) {
-    if (uint32_t(k) < w) {
-      hb += wsum[k];
-      nb += wsum[WAVES + k];
+  if (threadIdx.x == 0) {   // class starts, largest class first
+    uint32_t run = 0;
+    for (int c = int(ORDER_CLASSES) - 1; c >= 0; --c) {
+      const uint32_t k = cursor[c];
+      cursor[c] = run;
+      run += k;
     }
-    H += wsum[k];
   }
-  hb += ih - hv;
-  nb += H + in - nv;
+  __syncthreads();
 #pragma unroll
   for (uint32_t k = 0; k < ORDER_PER; ++k) {
     const uint32_t i = beg + k;
-    if (k < per && i < n) order[v[k] >= thr ? hb++ : nb++] = i;
+    if (k < per && i < n) order[lds_add(&cursor[cls[k]], 1)] = i;
   }
 }
 
