@@ -946,8 +946,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 }
 
 // ---------------------------------------------------------------------------
-// Order of the phase-C items, largest first (approximately: by the binary
-// order of magnitude of the entry count, a counting sort over 33 classes).
+// Order of the phase-C items, largest first (approximately: by half-octave
+// classes of the entry count, a counting sort over 65 classes).
 // A row bucket that holds a dominant source takes several times longer than
 // the others; the work queue hands positions out in order, so large items
 // start at once instead of possibly last, where they would set the kernel's
@@ -960,7 +960,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 // ---------------------------------------------------------------------------
 
 constexpr uint32_t ORDER_PER = NSGC_ORDER_MAX / NSGC_BLOCK;
-constexpr uint32_t ORDER_CLASSES = 33;   // 0 for empty items, else 1 + floor(log2(size))
+// 0 for empty items, else 1 + 2 floor(log2(size)) + the bit below the leading one
+constexpr uint32_t ORDER_CLASSES = 65;
 
 __global__ __launch_bounds__(NSGC_BLOCK) void k_order(nsgc_dev_plan* P) {
   __shared__ uint32_t cursor[ORDER_CLASSES];
@@ -977,7 +978,12 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_order(nsgc_dev_plan* P) {
   for (uint32_t k = 0; k < ORDER_PER; ++k) {
     const uint32_t i = beg + k;
     const uint32_t v = (k < per && i < n) ? sz[i] : 0u;
-    cls[k] = v ? 32u - uint32_t(__builtin_clz(v)) : 0u;
+    if (v) {
+      const uint32_t lg = 31u - uint32_t(__builtin_clz(v));
+      cls[k] = 1u + 2u * lg + (lg ? (v >> (lg - 1u)) & 1u : 0u);
+    } else {
+      cls[k] = 0u;
+    }
     if (k < per && i < n) lds_add(&cursor[cls[k]], 1);
   }
   __syncthreads();
