@@ -279,10 +279,26 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* red) {
 }
 
 // Two independent in-place exclusive scans, of a[0..na) and b[0..nb), with
-// one pair of barriers; a[na] and b[nb] receive the totals.  `red` is LDS
+// one pair of barriers (one barrier when both fit one wavefront); a[na] and
+// b[nb] receive the totals.  `red` is LDS
 // scratch of 2*WAVES words.
 __device__ __forceinline__ void block_exclusive_scan2(uint32_t* a, uint32_t na, uint32_t* b,
                                                       uint32_t nb, uint32_t* red) {
+  if (na <= 64 && nb <= 64) {   // one wavefront, one barrier
+    if (threadIdx.x < 64) {
+      const uint32_t l = threadIdx.x;
+      const uint32_t x = l < na ? a[l] : 0u, y = l < nb ? b[l] : 0u;
+      const uint32_t ix = wave_inclusive_scan(x), iy = wave_inclusive_scan(y);
+      if (l < na) a[l] = ix - x;
+      if (l < nb) b[l] = iy - y;
+      if (l == 63) {   // lanes at and above na (nb) add nothing: the totals
+        a[na] = ix;
+        b[nb] = iy;
+      }
+    }
+    __syncthreads();
+    return;
+  }
   const uint32_t pa = (na + NSGC_BLOCK - 1) / NSGC_BLOCK, pb = (nb + NSGC_BLOCK - 1) / NSGC_BLOCK;
   const uint32_t a0 = min(na, threadIdx.x * pa), a1 = min(na, a0 + pa);
   const uint32_t b0 = min(nb, threadIdx.x * pb), b1 = min(nb, b0 + pb);

@@ -830,20 +830,22 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
       }
       __syncthreads();
     };
+    // Counts -> starts (the caller's barrier must follow before emission,
+    // whose atomics advance the starts).
     auto publish = [&]() {
-      // the counts go to the phase-C items' sizes (a scheduling hint: large
-      // items are started first) before the scan turns them into starts
-      if (P->order_items) {
-        NSGC_GLOBAL uint32_t* sz = gptr(P->rcsize) + sload(P->prefC + wi);
-        for (uint32_t i = threadIdx.x; i < R + C; i += NSGC_BLOCK) {
-          const uint32_t v = i < R ? histR[i] : histC[i - R];
-          if (v) __hip_atomic_fetch_add(sz + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
       block_exclusive_scan2(histR, R, histC, C, st.red);
       for (uint32_t i = threadIdx.x; i <= R; i += NSGC_BLOCK) rec[B + u64(i) * B + b] = histR[i];
       for (uint32_t i = threadIdx.x; i <= C; i += NSGC_BLOCK)
         rec[B + u64(R + 1) * B + u64(i) * B + b] = histC[i];
+      // the counts also go to the phase-C items' sizes (a scheduling hint:
+      // large items are started first)
+      if (P->order_items) {
+        NSGC_GLOBAL uint32_t* sz = gptr(P->rcsize) + sload(P->prefC + wi);
+        for (uint32_t i = threadIdx.x; i < R + C; i += NSGC_BLOCK) {
+          const uint32_t v = i < R ? histR[i + 1] - histR[i] : histC[i - R + 1] - histC[i - R];
+          if (v) __hip_atomic_fetch_add(sz + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
     };
 
     // Attempt with 2^logS sweeps; any insert that gives up restarts the whole
