@@ -187,6 +187,17 @@ int nsgc_plan_inspect(const int64_t* window_offsets, int64_t num_windows,
                       int64_t* tiles, int64_t* workspace_bytes);
 
 /*
+ * Host-only sizing (no device work).  For the batch given by window_offsets,
+ * under the current tuning: the bytes of its device plan and of its
+ * workspace, and the upper bounds that nsgc_reserve and nsgc_graph_create
+ * use for any batch of at most as many packets and windows.  The actual
+ * sizes never exceed the bounds.  Any output pointer may be NULL.
+ */
+int nsgc_plan_sizes(const int64_t* window_offsets, int64_t num_windows, int64_t* plan_bytes,
+                    int64_t* workspace_bytes, int64_t* plan_bound_bytes,
+                    int64_t* workspace_bound_bytes);
+
+/*
  * Graph form: a reusable hipGraph of the batched form with its own workspace
  * sized for up to max_packets packets and max_windows windows.  Launching
  * replays the captured graph (plan upload + persistent kernels, fixed grids);

@@ -57,6 +57,7 @@ EXPORTS = (
     "nsgc_set_tune",
     "nsgc_default_tune",
     "nsgc_plan_inspect",
+    "nsgc_plan_sizes",
     "nsgc_graph_create",
     "nsgc_graph_launch",
     "nsgc_graph_destroy",
@@ -151,6 +152,8 @@ def _lib():
         lib.nsgc_default_tune.restype = i32
         lib.nsgc_plan_inspect.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
         lib.nsgc_plan_inspect.restype = i32
+        lib.nsgc_plan_sizes.argtypes = [vp, i64, vp, vp, vp, vp]
+        lib.nsgc_plan_sizes.restype = i32
         lib.nsgc_graph_create.argtypes = [i64, i64, ctypes.POINTER(vp)]
         lib.nsgc_graph_create.restype = i32
         lib.nsgc_graph_launch.argtypes = [vp, vp, vp, vp, i64, vp, vp]
@@ -302,6 +305,18 @@ def plan_inspect(offsets) -> dict:
     _check(rc, "nsgc_plan_inspect")
     return {"tier": tier[:w], "log2_link_buckets": lb[:w], "log2_row_buckets": lr[:w],
             "log2_col_buckets": lc[:w], "tiles": tiles[:w], "workspace_bytes": int(wsb[0])}
+
+
+def plan_sizes(offsets) -> dict:
+    """Host-only: the batch's plan and workspace bytes and the bounds used to
+    pre-size them for batches of as many packets and windows (no GPU needed)."""
+    off = _offsets(offsets)
+    v = np.zeros(4, np.int64)
+    rc = _lib().nsgc_plan_sizes(ctypes.c_void_p(off.ctypes.data), len(off) - 1,
+                                *(ctypes.c_void_p(v.ctypes.data + 8 * k) for k in range(4)))
+    _check(rc, "nsgc_plan_sizes")
+    return {"plan_bytes": int(v[0]), "workspace_bytes": int(v[1]), "plan_bound": int(v[2]),
+            "workspace_bound": int(v[3])}
 
 
 class Graph:

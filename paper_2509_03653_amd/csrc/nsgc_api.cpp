@@ -493,6 +493,31 @@ int nsgc_set_tune(const nsgc_tune* tune) {
   return NSGC_OK;
 }
 
+int nsgc_plan_sizes(const int64_t* window_offsets, int64_t num_windows, int64_t* plan_bytes,
+                    int64_t* workspace_bytes, int64_t* plan_bound_bytes,
+                    int64_t* workspace_bound_bytes) {
+  if (num_windows < 0) return NSGC_ERR_INVALID_ARG;
+  if (num_windows > 0 && !window_offsets) return NSGC_ERR_INVALID_ARG;
+  if (num_windows > 0) {
+    const int rc = validate_offsets(window_offsets, num_windows);
+    if (rc != NSGC_OK) return rc;
+  }
+  nsgc_tune t;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    t = current_tune();
+  }
+  HostPlan hp;
+  const int rc = make_plan(window_offsets, num_windows, t, &hp);
+  if (rc != NSGC_OK) return rc;
+  const int64_t P = num_windows > 0 ? window_offsets[num_windows] - window_offsets[0] : 0;
+  if (plan_bytes) *plan_bytes = int64_t(hp.plan_bytes());
+  if (workspace_bytes) *workspace_bytes = int64_t(hp.layout().total);
+  if (plan_bound_bytes) *plan_bound_bytes = int64_t(plan_bound(P, num_windows, t));
+  if (workspace_bound_bytes) *workspace_bound_bytes = int64_t(workspace_bound(P, num_windows, t));
+  return NSGC_OK;
+}
+
 int nsgc_plan_inspect(const int64_t* window_offsets, int64_t num_windows, int32_t* tier,
                       int32_t* log2_link_buckets, int32_t* log2_row_buckets,
                       int32_t* log2_col_buckets, int64_t* tiles, int64_t* workspace_bytes) {

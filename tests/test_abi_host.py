@@ -136,3 +136,41 @@ def test_no_cpu_path():
     s = torch.zeros(4, dtype=torch.int32)
     with pytest.raises(ValueError):
         nsgc.window_stats(s, s, [0, 4])
+
+
+@pytest.mark.parametrize("tune", [
+    {},
+    {"cls": [[64, 64, 64]] * 33, "max_link_buckets_log2": 12, "max_rc_buckets_log2": 12,
+     "small_max": 0},
+    {"tile_log2": 11, "small_max": 0, "max_link_buckets_log2": 12},
+    {"max_link_buckets_log2": 0, "max_rc_buckets_log2": 0, "small_max": 2048},
+    {"cls": [[100, 300, 70]] * 33, "tile_log2": 13},
+])
+def test_plan_and_workspace_within_their_bounds(tune):
+    # The graph form and nsgc_reserve size the plan buffer and the workspace
+    # from bounds that depend only on the packet and window counts; every
+    # batch of those counts must fit them.
+    base = nsgc.default_tune().to_dict()
+    base.update(tune)
+    before = nsgc.get_tune()
+    nsgc.set_tune(nsgc.Tune.from_dict(base))
+    try:
+        rng = np.random.default_rng(11)
+        for trial in range(60):
+            w = int(rng.integers(1, 300))
+            kind = trial % 4
+            if kind == 0:      # log-uniform, 1 .. 2^24
+                sizes = np.floor(2.0 ** rng.uniform(0, 24, w)).astype(np.int64)
+            elif kind == 1:    # just above powers of two times the targets
+                sizes = (2 ** rng.integers(6, 22, w) + 1).astype(np.int64)
+            elif kind == 2:    # one large window among empty and tiny ones
+                sizes = rng.integers(0, 3, w).astype(np.int64)
+                sizes[rng.integers(0, w)] = int(rng.integers(1 << 20, 1 << 25))
+            else:              # all equal
+                sizes = np.full(w, int(2 ** rng.uniform(8, 20)), np.int64)
+            off = np.concatenate([[int(rng.integers(0, 1000))], sizes]).cumsum().astype(np.int64)
+            s = nsgc.plan_sizes(off)
+            assert 0 < s["plan_bytes"] <= s["plan_bound"], (tune, trial, s)
+            assert 0 < s["workspace_bytes"] <= s["workspace_bound"], (tune, trial, s)
+    finally:
+        nsgc.set_tune(before)
