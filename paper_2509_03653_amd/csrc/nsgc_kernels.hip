@@ -13,9 +13,10 @@
 // covers the elements left, so short items do not pay for idle slots.
 //
 // The kernels that take uneven items (small windows, phases B and C) draw them
-// from an atomic work queue; the partition kernel strides over its uniform
-// tiles.  Grids are persistent, so a captured graph replays any batch that
-// fits its workspace.
+// from a work queue (ItemQueue: a static first item per workgroup, then
+// per-class atomic counters); the partition kernel strides over its uniform
+// tiles.  Phase C may take its items in the order k_order writes.  Grids are
+// persistent, so a captured graph replays any batch that fits its workspace.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -269,7 +270,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
 // aligned).  An LDS histogram gives every packet its rank in its bucket, a
 // block scan gives the bucket starts, the keys are placed in LDS in bucket
 // order and leave in full coalesced lines.  The tile's bucket starts go to
-// the bucket-major tile table.
+// the bucket-major tile table.  Before its tiles, the grid also clears the
+// phase-C item sizes that phase B sums when the plan orders phase C.
 // ---------------------------------------------------------------------------
 
 size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2) {
@@ -491,13 +493,18 @@ __device__ __forceinline__ void gather_by_wave(uint32_t nseg, SegFn seg, BatchFn
 // one LDS address).  Every newly inserted slot is also appended to a list of
 // occupied slots, so everything after the inserts (statistics, emission and
 // resetting the table for the next item) costs per link, not per slot.  The
-// table gives the bucket's share of stats 0-2.  Its links are then combined
-// per source and per destination in the same LDS region and emitted as
-// (src, packets, links) grouped by row bucket and (dst, packets, links)
-// grouped by column bucket into the bucket's emission region, so phase C
-// receives one entry per (link bucket, id) instead of one per link: a source
-// with thousands of links no longer makes one row bucket many times larger
-// than the others.
+// table gives the bucket's share of stats 0-2.  Each link is then emitted as
+// a row entry (src, packets, links = 1) grouped by row bucket and a column
+// entry (dst, packets, 1) grouped by column bucket into the bucket's
+// emission region: the entries are counted per row and column bucket, the
+// counts scanned into starts (also published for phase C), and the entries
+// written at the starts; the emission pass also empties the table.
+//
+// With per-id combining (the COMBINE instantiation, tuning combine_probes >
+// 0) the links are first combined per source and per destination in the
+// same LDS region, so phase C receives one entry per (link bucket, id)
+// instead of one per link; it costs phase B more than it saves phase C on
+// the measured workloads, so it is off by default.
 //
 // If an insert gives up (more distinct keys than the table holds), the bucket
 // is split into 2^s sweeps by further hash bits and redone; the sweeps
@@ -1008,13 +1015,15 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_order(nsgc_dev_plan* P) {
 // ---------------------------------------------------------------------------
 // Phase C: aggregation of one row bucket (or column bucket).
 //
-// Gathers the bucket's (id, packets, links) entries -- at most one per id and
-// link bucket -- from every link bucket into an LDS table id -> (packets,
-// links): summing them yields r(s) and f(s) (or c(d) and g(d)) for every id
-// of the bucket, hence its share of stats 3-5 (or 6-8).  Entries that repeat
-// the first valid lane's id are pre-combined with one ballot and DPP sums.  As in phase B the occupied
-// slots are listed, and overflow splits the bucket into sweeps by id-hash
-// bits.
+// Gathers the bucket's (id, packets, links) entries -- one per link, or one
+// per id and link bucket with combining -- from every link bucket into an LDS
+// table id -> (packets, links): summing them yields r(s) and f(s) (or c(d)
+// and g(d)) for every id of the bucket, hence its share of stats 3-5 (or
+// 6-8).  Entries that repeat the first valid lane's id are pre-combined with
+// one ballot and DPP sums.  One pass over the table folds the occupied slots
+// into the statistics and empties it, and overflow splits the bucket into
+// sweeps by id-hash bits.  Items are taken largest first when phase B's
+// sizes were ordered (see k_order).
 // ---------------------------------------------------------------------------
 
 size_t lds_rc_bytes(uint32_t slots_log2) {
