@@ -141,6 +141,18 @@ def test_large_window_short_segments(link_cap):
     check(src, dst, wl.offsets, f"large windows link cap 2^{link_cap}")
 
 
+@pytest.mark.parametrize("windows", [256, 257])
+def test_phase_c_order_limit(windows):
+    # 2^17-packet windows have 32 row and 32 column buckets: 256 windows give
+    # exactly 16384 phase-C items (taken largest first), 257 windows one
+    # window more (taken in their own order)
+    wl = synth.zipf_batch(seed=8, num_windows=windows, log2_window=17)
+    p = nsgc.plan_inspect(wl.offsets)
+    assert int(np.sum((1 << p["log2_row_buckets"]) + (1 << p["log2_col_buckets"]))) == 64 * windows
+    src, dst = wl.generate()
+    check(src, dst, wl.offsets, f"{windows} x 2^17 (phase-C order limit)")
+
+
 TUNES = {
     "tiny_tables_forced_sweeps": dict(link_slots_log2=10, rc_slots_log2=10,
                                       cls=[[65536, 65536, 65536]] * 33),
