@@ -343,9 +343,12 @@ __device__ __forceinline__ void block_exclusive_scan2(uint32_t* a, uint32_t na, 
 }
 
 // In-place exclusive scan of a[0..n) in LDS; a[n] receives the total, which is
-// also returned to every thread.  `red` is LDS scratch of WAVES words.
+// also returned to every thread (of an NT-thread block).  `red` is LDS
+// scratch of NT / 64 words.
+template <uint32_t NT = NSGC_BLOCK>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t* a, uint32_t n, uint32_t* red) {
-  const uint32_t per = (n + NSGC_BLOCK - 1) / NSGC_BLOCK;
+  constexpr int NW = int(NT / 64);
+  const uint32_t per = (n + NT - 1) / NT;
   const uint32_t beg = min(n, threadIdx.x * per);
   const uint32_t end = min(n, beg + per);
   uint32_t s = 0;
@@ -356,7 +359,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t* a, uint32_t n
   __syncthreads();
   uint32_t before = 0, total = 0;
 #pragma unroll
-  for (int k = 0; k < WAVES; ++k) {
+  for (int k = 0; k < NW; ++k) {
     const uint32_t t = red[k];
     if (uint32_t(k) < w) before += t;
     total += t;

@@ -78,6 +78,8 @@ constexpr u64 NSGC_INVALID_BIT = 1ull << 63;
 // Phase B holds 64-bit keys; four elements per thread keep it within 128
 // VGPRs, i.e. two 512-thread workgroups per compute unit.
 constexpr int LINK_MAXU = 4;
+// Tile 2^14 of phase A runs with NSGC_BLOCK * PART14_SCALE threads.
+constexpr int PART14_SCALE = 2;
 // Work-queue classes of phase B (at most NSGC_QCLASSES): one measured best;
 // its prefetched atomic hides behind the item.
 constexpr uint32_t LINK_QCLASSES = 1;
@@ -278,12 +280,12 @@ size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2) {
   return align16((max_link_buckets + 1) * 4) + align16((size_t(1) << tile_log2) * 8) + 256;
 }
 
-template <int PER>
-__global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* __restrict__ P,
-                                                          uint32_t max_link_buckets) {
+template <int PER, int NT = NSGC_BLOCK>
+__global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restrict__ P,
+                                                  uint32_t max_link_buckets) {
   static_assert(PER % 4 == 0, "PER must be a multiple of 4");
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr uint32_t T = NSGC_BLOCK * PER;
+  constexpr uint32_t T = NT * PER;
   uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
   u64* stage = reinterpret_cast<u64*>(smem + align16((max_link_buckets + 1) * 4));
   uint32_t* red = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(stage) + T * 8);
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* _
   if (P->order_items) {
     NSGC_GLOBAL uint32_t* sz = gptr(P->rcsize);
     const uint32_t nc = P->itemsC;
-    for (uint32_t i = blockIdx.x * NSGC_BLOCK + threadIdx.x; i < nc; i += gridDim.x * NSGC_BLOCK)
+    for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < nc; i += gridDim.x * NT)
       sz[i] = 0;
   }
   const uint32_t items = P->itemsA;
@@ -302,7 +304,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* _
     const uint32_t B = 1u << W.logB;
     const uint32_t tbeg = t * T;
     const uint32_t len = min(T, W.n - tbeg);
-    for (uint32_t i = threadIdx.x; i < B; i += NSGC_BLOCK) hist[i] = 0;
+    for (uint32_t i = threadIdx.x; i < B; i += NT) hist[i] = 0;
     if (t == 0 && threadIdx.x < 9) gptr(P->out)[u64(W.out_index) * 9 + threadIdx.x] = 0;
     __syncthreads();
 
@@ -318,7 +320,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* _
       // full aligned tile: each thread loads 4 consecutive packets per step
 #pragma unroll
       for (int k = 0; k < PER / 4; ++k) {
-        const uint32_t idx = (k * NSGC_BLOCK + threadIdx.x) * 4;
+        const uint32_t idx = (k * NT + threadIdx.x) * 4;
         const v4u32 s4 = *(const NSGC_GLOBAL v4u32*)(src + idx);
         const v4u32 d4 = *(const NSGC_GLOBAL v4u32*)(dst + idx);
         key[4 * k + 0] = (u64(s4.x) << 32) | d4.x;
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* _
     } else {
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
-        const uint32_t idx = k * NSGC_BLOCK + threadIdx.x;
+        const uint32_t idx = k * NT + threadIdx.x;
         ok[k] = idx < len;
         key[k] = ok[k] ? ((u64(src[idx]) << 32) | dst[idx]) : 0ull;
       }
@@ -343,15 +345,15 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_partition(const nsgc_dev_plan* _
       }
     }
     __syncthreads();
-    block_exclusive_scan(hist, B, red);
+    block_exclusive_scan<NT>(hist, B, red);
 #pragma unroll
     for (int k = 0; k < PER; ++k)
       if (ok[k]) stage[hist[br[k] & 0xFFFu] + (br[k] >> 12)] = key[k];
     NSGC_GLOBAL uint32_t* tm = gptr(P->tilemeta) + W.tilemeta + t;
-    for (uint32_t i = threadIdx.x; i <= B; i += NSGC_BLOCK) tm[u64(i) * W.ntiles] = hist[i];
+    for (uint32_t i = threadIdx.x; i <= B; i += NT) tm[u64(i) * W.ntiles] = hist[i];
     __syncthreads();
     NSGC_GLOBAL u64* out = gptr(P->keys) + W.ws + tbeg;
-    for (uint32_t i = threadIdx.x; i < len; i += NSGC_BLOCK) out[i] = stage[i];
+    for (uint32_t i = threadIdx.x; i < len; i += NT) out[i] = stage[i];
     __syncthreads();
   }
 }
@@ -1211,7 +1213,7 @@ hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t
     case 11: hipLaunchKernelGGL(k_partition<4>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
     case 12: hipLaunchKernelGGL(k_partition<8>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
     case 13: hipLaunchKernelGGL(k_partition<16>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
-    case 14: hipLaunchKernelGGL(k_partition<32>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
+    case 14: hipLaunchKernelGGL((k_partition<32 / PART14_SCALE, NSGC_BLOCK * PART14_SCALE>), dim3(grid), dim3(NSGC_BLOCK * PART14_SCALE), lds, s, P, max_link_buckets); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1247,7 +1249,7 @@ hipError_t resident_blocks(int which, uint32_t tile_log2, size_t lds, int* block
         case 11: f = reinterpret_cast<const void*>(&k_partition<4>); break;
         case 12: f = reinterpret_cast<const void*>(&k_partition<8>); break;
         case 13: f = reinterpret_cast<const void*>(&k_partition<16>); break;
-        case 14: f = reinterpret_cast<const void*>(&k_partition<32>); break;
+        case 14: f = reinterpret_cast<const void*>(&k_partition<32 / PART14_SCALE, NSGC_BLOCK * PART14_SCALE>); break;
         default: return hipErrorInvalidValue;
       }
       break;
@@ -1256,7 +1258,8 @@ hipError_t resident_blocks(int which, uint32_t tile_log2, size_t lds, int* block
     case 3: f = reinterpret_cast<const void*>(&k_rowcol); break;
     default: return hipErrorInvalidValue;
   }
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, NSGC_BLOCK, lds);
+  const int threads = which == 1 && tile_log2 == 14 ? NSGC_BLOCK * PART14_SCALE : NSGC_BLOCK;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, threads, lds);
 }
 
 hipError_t allow_large_lds(size_t bytes) {
@@ -1266,7 +1269,7 @@ hipError_t allow_large_lds(size_t bytes) {
       reinterpret_cast<const void*>(&k_links<true>),
       reinterpret_cast<const void*>(&k_rowcol),        reinterpret_cast<const void*>(&k_partition<4>),
       reinterpret_cast<const void*>(&k_partition<8>),  reinterpret_cast<const void*>(&k_partition<16>),
-      reinterpret_cast<const void*>(&k_partition<32>)};
+      reinterpret_cast<const void*>(&k_partition<32 / PART14_SCALE, NSGC_BLOCK * PART14_SCALE>)};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
