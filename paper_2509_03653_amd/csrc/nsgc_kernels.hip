@@ -83,7 +83,9 @@ constexpr int PART14_SCALE = 2;
 // Work-queue classes of phase B (at most NSGC_QCLASSES): one measured best;
 // its prefetched atomic hides behind the item.
 constexpr uint32_t LINK_QCLASSES = 1;
-constexpr int RC_MAXU = 8;
+// Phase C: four as well; eight spilled registers under its 80-VGPR budget
+// (six waves per SIMD) and measured slower.
+constexpr int RC_MAXU = 4;
 // Links a thread holds while phase B combines them per source and
 // destination: the link table has at most LK * NSGC_BLOCK slots.
 constexpr int LK = 8;
