@@ -416,7 +416,7 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
 
 // The packed walk is taken when it needs fewer than PACK_NUM / PACK_DEN of
 // the segment-by-segment walk's chunks (its search costs part of a chunk).
-constexpr uint32_t PACK_NUM = 3, PACK_DEN = 4;
+constexpr uint32_t PACK_NUM = 7, PACK_DEN = 8;
 
 template <int MAXU, class SegFn, class BatchFn>
 __device__ __forceinline__ void gather_by_wave(uint32_t nseg, SegFn seg, BatchFn fn) {
