@@ -47,6 +47,11 @@
  *   - The library keeps per-(device, stream) workspaces, so calls on
  *     different streams may overlap; calls on one stream run in order.  All
  *     entry points are thread-safe.
+ *   - The direct forms (nsgc_window_stats, _plain, _timed) must not be
+ *     called on a stream that is being captured: they return
+ *     NSGC_ERR_CAPTURING with nothing enqueued.  Their plan upload reads a
+ *     staging buffer that later calls overwrite, so a replay would not be
+ *     the same call.  Capture-safe batching is the graph form below.
  */
 #ifndef NSGC_H_
 #define NSGC_H_
@@ -77,7 +82,7 @@ typedef enum nsgc_status {
   NSGC_ERR_NO_MEMORY = -3,    /* workspace allocation failed or exceeds limit */
   NSGC_ERR_HIP = -4,          /* HIP runtime error, see nsgc_last_hip_error() */
   NSGC_ERR_INTERNAL = -5,
-  NSGC_ERR_CAPTURING = -6     /* would allocate while the stream is capturing */
+  NSGC_ERR_CAPTURING = -6     /* called on a stream that is being captured */
 } nsgc_status;
 
 /*
@@ -101,6 +106,15 @@ int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
                             nsgc_stats* out_stats, void* stream);
 
 /*
+ * Process-wide switch for comparisons: with on != 0, nsgc_window_stats runs
+ * the plain form (one window per launch sequence, no batching); 0 restores
+ * the batched form (the default).  The graph form is not affected.  Always
+ * returns NSGC_OK.  nsgc_get_plain_mode returns the current setting (0/1).
+ */
+int nsgc_set_plain_mode(int on);
+int nsgc_get_plain_mode(void);
+
+/*
  * Measurement form: the batched form with HIP events recorded on `stream`
  * around each kernel launch.  Waits for the work to finish and writes the
  * elapsed milliseconds of the four launches to phase_ms[0..3]: small-window
@@ -119,11 +133,18 @@ const char* nsgc_status_string(int status);
 int nsgc_last_hip_error(void);
 
 /*
- * Pre-size the workspace of (current device, stream) for batches of up to
+ * Pre-size the workspace pool of the current device for batches of up to
  * max_packets packets in up to max_windows windows, so that later calls
- * within those limits allocate nothing.  Returns NSGC_OK or NSGC_ERR_*.
+ * within those limits allocate nothing.  nsgc_reserve sizes the pool entry
+ * of the null stream (the default stream of the current device);
+ * nsgc_reserve_stream that of `stream` (each stream has its own entry, so
+ * calls on different streams may overlap).  Waits for the stream when an
+ * existing buffer has to grow.  Returns NSGC_OK, NSGC_ERR_INVALID_ARG
+ * (negative sizes), NSGC_ERR_NO_MEMORY, NSGC_ERR_CAPTURING (stream being
+ * captured) or NSGC_ERR_HIP.
  */
-int nsgc_reserve(int64_t max_packets, int64_t max_windows, void* stream);
+int nsgc_reserve(int64_t max_packets, int64_t max_windows);
+int nsgc_reserve_stream(int64_t max_packets, int64_t max_windows, void* stream);
 
 /* Release all workspaces of the current device (waits for the device). */
 int nsgc_release(void);
@@ -202,8 +223,12 @@ int nsgc_plan_sizes(const int64_t* window_offsets, int64_t num_windows, int64_t*
  * sized for up to max_packets packets and max_windows windows.  Launching
  * replays the captured graph (plan upload + persistent kernels, fixed grids);
  * only the plan's contents change between launches, so any batch within the
- * limits reuses it.  Launches of one graph object must not overlap in time on
- * different streams; one stream per graph object is the intended use.
+ * limits reuses it.  Launches of one graph object are serialised: a launch on
+ * another stream than the previous one waits on the device for the previous
+ * launch to finish (the two instances share one workspace).  This is the
+ * form to use inside a caller's own stream capture: nsgc_graph_launch is not
+ * itself capturable (it plans on the host), but its work is one graph
+ * launch per call.
  */
 typedef struct nsgc_graph nsgc_graph;
 int nsgc_graph_create(int64_t max_packets, int64_t max_windows, nsgc_graph** out);

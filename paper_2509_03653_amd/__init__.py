@@ -51,7 +51,10 @@ EXPORTS = (
     "nsgc_window_stats_timed",
     "nsgc_status_string",
     "nsgc_last_hip_error",
+    "nsgc_set_plain_mode",
+    "nsgc_get_plain_mode",
     "nsgc_reserve",
+    "nsgc_reserve_stream",
     "nsgc_release",
     "nsgc_get_tune",
     "nsgc_set_tune",
@@ -140,8 +143,14 @@ def _lib():
         lib.nsgc_status_string.restype = ctypes.c_char_p
         lib.nsgc_last_hip_error.argtypes = []
         lib.nsgc_last_hip_error.restype = i32
-        lib.nsgc_reserve.argtypes = [i64, i64, vp]
+        lib.nsgc_set_plain_mode.argtypes = [i32]
+        lib.nsgc_set_plain_mode.restype = i32
+        lib.nsgc_get_plain_mode.argtypes = []
+        lib.nsgc_get_plain_mode.restype = i32
+        lib.nsgc_reserve.argtypes = [i64, i64]
         lib.nsgc_reserve.restype = i32
+        lib.nsgc_reserve_stream.argtypes = [i64, i64, vp]
+        lib.nsgc_reserve_stream.restype = i32
         lib.nsgc_release.argtypes = []
         lib.nsgc_release.restype = i32
         lib.nsgc_get_tune.argtypes = [ctypes.POINTER(Tune)]
@@ -260,10 +269,23 @@ def window_stats_timed(src, dst, offsets, out=None, stream=None):
 
 
 def reserve(max_packets: int, max_windows: int, stream=None):
-    import torch
-    _check(_lib().nsgc_reserve(int(max_packets), int(max_windows),
-                               _stream_handle(stream, torch.cuda.current_device())),
-           "nsgc_reserve")
+    """Pre-size the workspace of the null stream (``nsgc_reserve``), or of
+    ``stream`` when given (``nsgc_reserve_stream``)."""
+    if stream is None:
+        _check(_lib().nsgc_reserve(int(max_packets), int(max_windows)), "nsgc_reserve")
+        return
+    _check(_lib().nsgc_reserve_stream(int(max_packets), int(max_windows),
+                                      ctypes.c_void_p(int(stream.cuda_stream))),
+           "nsgc_reserve_stream")
+
+
+def set_plain_mode(on: bool):
+    """Route ``window_stats`` through the plain one-window-per-launch form."""
+    _check(_lib().nsgc_set_plain_mode(1 if on else 0), "nsgc_set_plain_mode")
+
+
+def plain_mode() -> bool:
+    return bool(_lib().nsgc_get_plain_mode())
 
 
 def release():

@@ -79,6 +79,7 @@ std::mutex g_mu;
 std::map<int, DevCtx*> g_devs;
 nsgc_tune g_tune;
 bool g_tune_set = false;
+bool g_plain_mode = false;   // nsgc_set_plain_mode: route nsgc_window_stats through the plain form
 
 const nsgc_tune& current_tune() {
   if (!g_tune_set) {
@@ -314,81 +315,28 @@ size_t workspace_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune
   return size_t(P * 24 + (tilemeta + lbmeta + 2 * items) * 4 + 8 * 256);
 }
 
-
-}  // namespace
-
-// ---------------------------------------------------------------------------
-
-extern "C" {
-
-const char* nsgc_status_string(int status) {
-  switch (status) {
-    case NSGC_OK: return "ok";
-    case NSGC_ERR_INVALID_ARG: return "invalid argument";
-    case NSGC_ERR_BAD_OFFSETS: return "bad window offsets (negative, decreasing, or a window of 2^32 or more packets)";
-    case NSGC_ERR_NO_MEMORY: return "device workspace allocation failed";
-    case NSGC_ERR_HIP: return "HIP runtime error";
-    case NSGC_ERR_INTERNAL: return "internal error";
-    case NSGC_ERR_CAPTURING: return "allocation needed while the stream is being captured";
-    default: return "unknown status";
-  }
-}
-
-int nsgc_last_hip_error(void) { return t_last_hip_error; }
-
-int nsgc_window_stats(const uint32_t* src, const uint32_t* dst, const int64_t* window_offsets,
-                      int64_t num_windows, nsgc_stats* out_stats, void* stream) {
-  int rc = validate_common(src, dst, window_offsets, num_windows, out_stats);
-  if (rc != NSGC_OK || num_windows == 0) return rc;
-  std::lock_guard<std::mutex> lock(g_mu);
+// The batched form (caller holds g_mu, arguments validated, num_windows > 0).
+int batched_locked(const uint32_t* src, const uint32_t* dst, const int64_t* window_offsets,
+                   int64_t num_windows, nsgc_stats* out_stats, hipStream_t s) {
   const nsgc_tune t = current_tune();
   HostPlan hp;
+  int rc;
   if ((rc = make_plan(window_offsets, num_windows, t, &hp)) != NSGC_OK) return rc;
   DevCtx* c = nullptr;
   if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
-  const hipStream_t s = static_cast<hipStream_t>(stream);
   Slot* sl = nullptr;
   if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
   return run_plan(c, sl, hp, t, src, dst, out_stats, s);
 }
 
-int nsgc_window_stats_timed(const uint32_t* src, const uint32_t* dst,
-                            const int64_t* window_offsets, int64_t num_windows,
-                            nsgc_stats* out_stats, void* stream, float* phase_ms) {
-  if (!phase_ms) return NSGC_ERR_INVALID_ARG;
-  int rc = validate_common(src, dst, window_offsets, num_windows, out_stats);
-  if (rc != NSGC_OK) return rc;
-  for (int i = 0; i < 4; ++i) phase_ms[i] = 0.0f;
-  if (num_windows == 0) return NSGC_OK;
-  std::lock_guard<std::mutex> lock(g_mu);
-  const nsgc_tune t = current_tune();
-  HostPlan hp;
-  if ((rc = make_plan(window_offsets, num_windows, t, &hp)) != NSGC_OK) return rc;
-  DevCtx* c = nullptr;
-  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-  if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
-  Slot* sl = nullptr;
-  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
-  for (int i = 0; i < 5; ++i)
-    if (!sl->phase_ev[i]) NSGC_HIP(hipEventCreate(&sl->phase_ev[i]));
-  if ((rc = run_plan(c, sl, hp, t, src, dst, out_stats, s, sl->phase_ev)) != NSGC_OK) return rc;
-  NSGC_HIP(hipEventSynchronize(sl->phase_ev[4]));
-  for (int i = 0; i < 4; ++i)
-    NSGC_HIP(hipEventElapsedTime(&phase_ms[i], sl->phase_ev[i], sl->phase_ev[i + 1]));
-  return NSGC_OK;
-}
-
-int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
-                            const int64_t* window_offsets, int64_t num_windows,
-                            nsgc_stats* out_stats, void* stream) {
-  int rc = validate_common(src, dst, window_offsets, num_windows, out_stats);
-  if (rc != NSGC_OK || num_windows == 0) return rc;
-  std::lock_guard<std::mutex> lock(g_mu);
+// The plain form: one plan and one launch sequence per window (caller holds
+// g_mu, arguments validated, num_windows > 0).
+int plain_locked(const uint32_t* src, const uint32_t* dst, const int64_t* window_offsets,
+                 int64_t num_windows, nsgc_stats* out_stats, hipStream_t s) {
   const nsgc_tune t = current_tune();
   DevCtx* c = nullptr;
+  int rc;
   if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
-  const hipStream_t s = static_cast<hipStream_t>(stream);
   Slot* sl = nullptr;
   if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
   Launch L;
@@ -425,14 +373,13 @@ int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
   return NSGC_OK;
 }
 
-int nsgc_reserve(int64_t max_packets, int64_t max_windows, void* stream) {
-  if (max_packets < 0 || max_windows < 0) return NSGC_ERR_INVALID_ARG;
-  std::lock_guard<std::mutex> lock(g_mu);
+// Pre-size the workspace, plan buffer and staging ring of (current device, s).
+int reserve_locked(int64_t max_packets, int64_t max_windows, hipStream_t s) {
+  if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
   const nsgc_tune t = current_tune();
   DevCtx* c = nullptr;
   int rc;
   if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
-  const hipStream_t s = static_cast<hipStream_t>(stream);
   Slot* sl = nullptr;
   if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
   const size_t pb = plan_bound(max_packets, max_windows, t);
@@ -445,6 +392,103 @@ int nsgc_reserve(int64_t max_packets, int64_t max_windows, void* stream) {
     if ((rc = take_stage(sl, pb, s, &idx)) != NSGC_OK) return rc;
   }
   return NSGC_OK;
+}
+
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* nsgc_status_string(int status) {
+  switch (status) {
+    case NSGC_OK: return "ok";
+    case NSGC_ERR_INVALID_ARG: return "invalid argument";
+    case NSGC_ERR_BAD_OFFSETS: return "bad window offsets (negative, decreasing, or a window of 2^32 or more packets)";
+    case NSGC_ERR_NO_MEMORY: return "device workspace allocation failed";
+    case NSGC_ERR_HIP: return "HIP runtime error";
+    case NSGC_ERR_INTERNAL: return "internal error";
+    case NSGC_ERR_CAPTURING: return "allocation needed while the stream is being captured";
+    default: return "unknown status";
+  }
+}
+
+int nsgc_last_hip_error(void) { return t_last_hip_error; }
+
+int nsgc_window_stats(const uint32_t* src, const uint32_t* dst, const int64_t* window_offsets,
+                      int64_t num_windows, nsgc_stats* out_stats, void* stream) {
+  int rc = validate_common(src, dst, window_offsets, num_windows, out_stats);
+  if (rc != NSGC_OK || num_windows == 0) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  // The plan travels through a rotating staging ring and a per-stream
+  // workspace that later calls reuse, so a captured call could not be
+  // replayed safely: capture the graph form (nsgc_graph_*) instead.
+  if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (g_plain_mode) return plain_locked(src, dst, window_offsets, num_windows, out_stats, s);
+  return batched_locked(src, dst, window_offsets, num_windows, out_stats, s);
+}
+
+int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
+                            const int64_t* window_offsets, int64_t num_windows,
+                            nsgc_stats* out_stats, void* stream) {
+  int rc = validate_common(src, dst, window_offsets, num_windows, out_stats);
+  if (rc != NSGC_OK || num_windows == 0) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
+  std::lock_guard<std::mutex> lock(g_mu);
+  return plain_locked(src, dst, window_offsets, num_windows, out_stats, s);
+}
+
+int nsgc_set_plain_mode(int on) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_plain_mode = on != 0;
+  return NSGC_OK;
+}
+
+int nsgc_get_plain_mode(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  return g_plain_mode ? 1 : 0;
+}
+
+int nsgc_window_stats_timed(const uint32_t* src, const uint32_t* dst,
+                            const int64_t* window_offsets, int64_t num_windows,
+                            nsgc_stats* out_stats, void* stream, float* phase_ms) {
+  if (!phase_ms) return NSGC_ERR_INVALID_ARG;
+  int rc = validate_common(src, dst, window_offsets, num_windows, out_stats);
+  if (rc != NSGC_OK) return rc;
+  for (int i = 0; i < 4; ++i) phase_ms[i] = 0.0f;
+  if (num_windows == 0) return NSGC_OK;
+  std::lock_guard<std::mutex> lock(g_mu);
+  const nsgc_tune t = current_tune();
+  HostPlan hp;
+  if ((rc = make_plan(window_offsets, num_windows, t, &hp)) != NSGC_OK) return rc;
+  DevCtx* c = nullptr;
+  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
+  Slot* sl = nullptr;
+  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
+  for (int i = 0; i < 5; ++i)
+    if (!sl->phase_ev[i]) NSGC_HIP(hipEventCreate(&sl->phase_ev[i]));
+  if ((rc = run_plan(c, sl, hp, t, src, dst, out_stats, s, sl->phase_ev)) != NSGC_OK) return rc;
+  NSGC_HIP(hipEventSynchronize(sl->phase_ev[4]));
+  for (int i = 0; i < 4; ++i)
+    NSGC_HIP(hipEventElapsedTime(&phase_ms[i], sl->phase_ev[i], sl->phase_ev[i + 1]));
+  return NSGC_OK;
+}
+
+int nsgc_reserve(int64_t max_packets, int64_t max_windows) {
+  if (max_packets < 0 || max_windows < 0) return NSGC_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  return reserve_locked(max_packets, max_windows, nullptr);
+}
+
+int nsgc_reserve_stream(int64_t max_packets, int64_t max_windows, void* stream) {
+  if (max_packets < 0 || max_windows < 0) return NSGC_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  return reserve_locked(max_packets, max_windows, static_cast<hipStream_t>(stream));
 }
 
 int nsgc_release(void) {
@@ -570,6 +614,7 @@ struct nsgc_graph {
     hipGraph_t graph[4] = {};     // indexed by plan variant (see plan_variant)
     hipGraphExec_t exec[4] = {};
     hipEvent_t done = nullptr;
+    hipStream_t stream = nullptr;  // stream of the last launch
     bool used = false;
   } inst[2];
   int next = 0;
@@ -698,8 +743,13 @@ int nsgc_graph_launch(nsgc_graph* g, const uint32_t* src, const uint32_t* dst,
   if (!in.exec[variant] && (rc = capture_instance(g, in, variant)) != NSGC_OK) return rc;
   hp.serialize(in.stage, reinterpret_cast<uint64_t>(in.plan_dev), reinterpret_cast<uint64_t>(g->ws),
                src, dst, out_stats);
+  // Both instances share the workspace: a launch on another stream than the
+  // other instance's last one waits (on the device) for that launch to end.
+  const nsgc_graph::Inst& other = g->inst[g->next ^ 1];
+  if (other.used && other.stream != s) NSGC_HIP(hipStreamWaitEvent(s, other.done, 0));
   NSGC_HIP(hipGraphLaunch(in.exec[variant], s));
   NSGC_HIP(hipEventRecord(in.done, s));
+  in.stream = s;
   in.used = true;
   g->next ^= 1;
   return NSGC_OK;

@@ -174,3 +174,21 @@ def test_plan_and_workspace_within_their_bounds(tune):
             assert 0 < s["workspace_bytes"] <= s["workspace_bound"], (tune, trial, s)
     finally:
         nsgc.set_tune(before)
+
+
+def test_plain_mode_switch_is_host_state():
+    assert nsgc.plain_mode() is False
+    nsgc.set_plain_mode(True)
+    try:
+        assert nsgc.plain_mode() is True
+    finally:
+        nsgc.set_plain_mode(False)
+    assert nsgc.plain_mode() is False
+
+
+def test_reserve_rejects_negative_sizes_before_device_work():
+    lib = nsgc.library()
+    assert lib.nsgc_reserve(-1, 4) == -1
+    assert lib.nsgc_reserve(4, -1) == -1
+    assert lib.nsgc_reserve_stream(-1, 4, ctypes.c_void_p(0)) == -1
+    assert lib.nsgc_reserve_stream(4, -1, ctypes.c_void_p(0)) == -1

@@ -326,3 +326,74 @@ def test_abandoned_bucket_is_reported_not_hung():
     # the default sweep limit handles the same batch exactly
     nsgc.set_tune(nsgc.default_tune())
     assert_same(gpu_stats(src, dst, off), want, "default sweeps")
+
+
+def test_plain_mode_routes_the_batched_entry_point():
+    rng = np.random.default_rng(31)
+    sizes = [0, 5, 3000, 70000, 1]
+    off = synth.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    src = rng.integers(0, 300, n).astype(np.uint32)
+    dst = rng.integers(0, 900, n).astype(np.uint32)
+    want = oracle.window_stats(src, dst, off)
+    nsgc.set_plain_mode(True)
+    try:
+        say("[gpu] plain mode through nsgc_window_stats")
+        assert_same(gpu_stats(src, dst, off, "batched"), want, "plain mode")
+    finally:
+        nsgc.set_plain_mode(False)
+    assert_same(gpu_stats(src, dst, off, "batched"), want, "batched mode")
+
+
+def test_direct_forms_refuse_a_capturing_stream():
+    # A direct call inside a stream capture returns NSGC_ERR_CAPTURING with
+    # nothing enqueued; the capture itself stays valid and ends normally.
+    import ctypes
+    import torch
+    from gpu_util import to_gpu
+    s = to_gpu(np.arange(4096, dtype=np.uint32))
+    off = np.array([0, 2048, 4096], np.int64)
+    out = torch.full((2, 9), -7, dtype=torch.int64, device="cuda")
+    lib = nsgc.library()
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    say("[gpu] direct forms under capture")
+    codes = []
+    with torch.cuda.graph(g, stream=stream):
+        h = ctypes.c_void_p(int(stream.cuda_stream))
+        for fn in (lib.nsgc_window_stats, lib.nsgc_window_stats_plain):
+            codes.append(fn(ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(s.data_ptr()),
+                            ctypes.c_void_p(off.ctypes.data), 2, ctypes.c_void_p(out.data_ptr()), h))
+        codes.append(lib.nsgc_reserve_stream(1 << 20, 16, h))
+        out.add_(0)                     # keep the captured graph non-empty
+    assert codes == [-6, -6, -6], codes
+    g.replay()
+    torch.cuda.synchronize()
+    assert bool((out == -7).all())      # nothing was enqueued into the graph
+
+
+def test_graph_launches_on_two_streams_are_serialised():
+    # One graph object launched alternately on two streams: every launch must
+    # see its own batch (the instances share one workspace).
+    import torch
+    from gpu_util import to_gpu
+    wl = synth.zipf_batch(seed=5, num_windows=6, log2_window=15)
+    src, dst = wl.generate()
+    off = wl.offsets
+    want = oracle.window_stats(src, dst, off, threads=8)
+    rev = np.ascontiguousarray(dst), np.ascontiguousarray(src)
+    want_rev = oracle.window_stats(rev[0], rev[1], off, threads=8)
+    g = nsgc.Graph(int(off[-1]), len(off) - 1)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    s1, d1 = to_gpu(src), to_gpu(dst)
+    outs = []
+    say("[gpu] graph on two streams")
+    for i in range(6):
+        a, b = (s1, d1) if i % 2 == 0 else (d1, s1)
+        outs.append(g.launch(a, b, off, stream=streams[i % 2]))
+    torch.cuda.synchronize()
+    g.close()
+    for i, o in enumerate(outs):
+        assert_same(o.cpu().numpy().view(np.uint64), want if i % 2 == 0 else want_rev,
+                    f"launch {i}")
