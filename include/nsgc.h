@@ -82,7 +82,8 @@ typedef enum nsgc_status {
   NSGC_ERR_NO_MEMORY = -3,    /* workspace allocation failed or exceeds limit */
   NSGC_ERR_HIP = -4,          /* HIP runtime error, see nsgc_last_hip_error() */
   NSGC_ERR_INTERNAL = -5,
-  NSGC_ERR_CAPTURING = -6     /* called on a stream that is being captured */
+  NSGC_ERR_CAPTURING = -6,    /* called on a stream that is being captured */
+  NSGC_ERR_TOO_LARGE = -7     /* batch exceeds nsgc_window_stats_noalloc's fixed scratch */
 } nsgc_status;
 
 /*
@@ -125,6 +126,32 @@ int nsgc_get_plain_mode(void);
 int nsgc_window_stats_timed(const uint32_t* src, const uint32_t* dst,
                             const int64_t* window_offsets, int64_t num_windows,
                             nsgc_stats* out_stats, void* stream, float* phase_ms);
+
+/*
+ * Fixed-scratch form, for callers that cannot allocate (code that must not
+ * call hipMalloc, such as tight serving loops or harnesses that forbid
+ * allocation).  Same arguments, results and rules as nsgc_window_stats, but
+ * the plan and the workspace live in one statically sized device array per
+ * GPU (NSGC_NOALLOC_SCRATCH_BYTES, of which the first NSGC_NOALLOC_PLAN_BYTES
+ * hold the plan), held by each GPU the call runs on until the process ends.
+ * No device memory and no pinned host memory is ever allocated; the plan is
+ * staged in ordinary host memory.  The workspace needs about 24 bytes per
+ * packet of the windows above 1024 packets, so batches of up to roughly
+ * 5.2 million such packets fit; a batch that does not fit returns
+ * NSGC_ERR_TOO_LARGE with nothing enqueued (nsgc_plan_sizes tells the plan
+ * and workspace bytes of a batch beforehand).  All calls on one GPU share
+ * its array, which keeps the last call's contents (each call rewrites what
+ * it reads).  Overlapping calls would race on it, so the library serialises
+ * them: a call on another stream than the previous call waits on the device
+ * for that call to finish.  Calls on different streams therefore never run
+ * concurrently in this form.  Not usable under stream capture
+ * (NSGC_ERR_CAPTURING).
+ */
+#define NSGC_NOALLOC_SCRATCH_BYTES (128ull << 20)
+#define NSGC_NOALLOC_PLAN_BYTES (2ull << 20)
+int nsgc_window_stats_noalloc(const uint32_t* src, const uint32_t* dst,
+                              const int64_t* window_offsets, int64_t num_windows,
+                              nsgc_stats* out_stats, void* stream);
 
 /* Human-readable text for a status code (static storage, never NULL). */
 const char* nsgc_status_string(int status);

@@ -42,6 +42,7 @@ STATUS = {
     -4: "NSGC_ERR_HIP",
     -5: "NSGC_ERR_INTERNAL",
     -6: "NSGC_ERR_CAPTURING",
+    -7: "NSGC_ERR_TOO_LARGE",
 }
 
 # Every function declared in include/nsgc.h.
@@ -49,6 +50,7 @@ EXPORTS = (
     "nsgc_window_stats",
     "nsgc_window_stats_plain",
     "nsgc_window_stats_timed",
+    "nsgc_window_stats_noalloc",
     "nsgc_status_string",
     "nsgc_last_hip_error",
     "nsgc_set_plain_mode",
@@ -137,6 +139,8 @@ def _lib():
         lib.nsgc_window_stats.restype = i32
         lib.nsgc_window_stats_plain.argtypes = [vp, vp, vp, i64, vp, vp]
         lib.nsgc_window_stats_plain.restype = i32
+        lib.nsgc_window_stats_noalloc.argtypes = [vp, vp, vp, i64, vp, vp]
+        lib.nsgc_window_stats_noalloc.restype = i32
         lib.nsgc_window_stats_timed.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         lib.nsgc_window_stats_timed.restype = i32
         lib.nsgc_status_string.argtypes = [i32]
@@ -254,6 +258,20 @@ def window_stats_plain(src, dst, offsets, out=None, stream=None):
     """Plain form (``nsgc_window_stats_plain``): one launch sequence per window."""
     return _run(_lib().nsgc_window_stats_plain, "nsgc_window_stats_plain", src, dst, offsets,
                 out, stream)
+
+
+def window_stats_noalloc(src, dst, offsets, out=None, stream=None):
+    """Fixed-scratch form (``nsgc_window_stats_noalloc``): the library
+    allocates nothing; pass ``out`` to keep the call allocation-free on the
+    Python side too.  Batches beyond the fixed scratch raise
+    NSGC_ERR_TOO_LARGE."""
+    return _run(_lib().nsgc_window_stats_noalloc, "nsgc_window_stats_noalloc", src, dst, offsets,
+                out, stream)
+
+
+# Fixed scratch of nsgc_window_stats_noalloc (include/nsgc.h).
+NOALLOC_SCRATCH_BYTES = 128 << 20
+NOALLOC_PLAN_BYTES = 2 << 20
 
 
 PHASES = ("small", "partition", "links", "rowcol")

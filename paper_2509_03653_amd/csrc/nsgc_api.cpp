@@ -66,6 +66,19 @@ struct Slot {
   hipEvent_t phase_ev[5] = {};  // timing events of nsgc_window_stats_timed
 };
 
+// State of the fixed-scratch form on one device: a host staging buffer for
+// its plan (ordinary host memory, sized once), the event after its last plan
+// copy (the staging buffer is rewritten only once that copy has read it) and
+// the event after its last launch (a call on another stream waits for it on
+// the device, since every call shares the device's one scratch array).
+struct FixedState {
+  std::vector<char> stage;
+  hipEvent_t copied = nullptr;
+  hipEvent_t done = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool used = false;
+};
+
 struct DevCtx {
   int device = 0;
   int cus = 256;
@@ -73,6 +86,7 @@ struct DevCtx {
   std::map<hipStream_t, Slot*> slots;
   // resident workgroups per CU by (kernel, tile_log2, dynamic LDS bytes)
   std::map<std::tuple<int, uint32_t, size_t>, int> resident;
+  FixedState fixed;
 };
 
 std::mutex g_mu;
@@ -397,6 +411,62 @@ int reserve_locked(int64_t max_packets, int64_t max_windows, hipStream_t s) {
 
 }  // namespace
 
+namespace nsgc {
+
+int validate_call(const uint32_t* src, const uint32_t* dst, const int64_t* offsets,
+                  int64_t num_windows, const void* out) {
+  return validate_common(src, dst, offsets, num_windows, out);
+}
+
+int record_hip_error(int e) { return hip_fail(hipError_t(e)); }
+
+// The batched form on caller-provided device buffers: `plan_dev` (plan_cap
+// bytes) receives the plan and `ws` (ws_cap bytes) serves as the workspace.
+// Nothing is allocated on the device or in pinned host memory: the plan is
+// staged in the device context's host buffer, sized once at the first call
+// on the device.  Batches whose plan or workspace exceed the buffers return
+// NSGC_ERR_TOO_LARGE with nothing enqueued.
+int run_fixed_scratch(const uint32_t* src, const uint32_t* dst, const int64_t* window_offsets,
+                      int64_t num_windows, nsgc_stats* out_stats, void* stream, char* plan_dev,
+                      size_t plan_cap, char* ws, size_t ws_cap) {
+  int rc = validate_common(src, dst, window_offsets, num_windows, out_stats);
+  if (rc != NSGC_OK || num_windows == 0) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
+  std::lock_guard<std::mutex> lock(g_mu);
+  const nsgc_tune t = current_tune();
+  HostPlan hp;
+  if ((rc = make_plan(window_offsets, num_windows, t, &hp)) != NSGC_OK) return rc;
+  const size_t pbytes = hp.plan_bytes();
+  const WsLayout lay = hp.layout();
+  if (pbytes > plan_cap || lay.total > ws_cap) return NSGC_ERR_TOO_LARGE;
+  DevCtx* c = nullptr;
+  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
+  Launch L;
+  if ((rc = launch_params(c, t, &L)) != NSGC_OK) return rc;
+  FixedState& f = c->fixed;
+  if (!f.copied) NSGC_HIP(hipEventCreateWithFlags(&f.copied, hipEventDisableTiming));
+  if (!f.done) NSGC_HIP(hipEventCreateWithFlags(&f.done, hipEventDisableTiming));
+  if (f.stage.size() < plan_cap) f.stage.resize(plan_cap);
+  // the previous call's plan copy must have read the staging buffer
+  if (f.used) NSGC_HIP(hipEventSynchronize(f.copied));
+  hp.serialize(f.stage.data(), reinterpret_cast<uint64_t>(plan_dev), reinterpret_cast<uint64_t>(ws),
+               src, dst, out_stats);
+  // every call on the device shares its scratch: order after the last one
+  if (f.used && f.last_stream != s) NSGC_HIP(hipStreamWaitEvent(s, f.done, 0));
+  NSGC_HIP(hipMemcpyAsync(plan_dev, f.stage.data(), pbytes, hipMemcpyHostToDevice, s));
+  NSGC_HIP(hipEventRecord(f.copied, s));
+  rc = enqueue_kernels(hp, reinterpret_cast<const nsgc_dev_plan*>(plan_dev), L, hp.tile_log2, s,
+                       false, 0);
+  if (rc != NSGC_OK) return rc;
+  NSGC_HIP(hipEventRecord(f.done, s));
+  f.last_stream = s;
+  f.used = true;
+  return NSGC_OK;
+}
+
+}  // namespace nsgc
+
 // ---------------------------------------------------------------------------
 
 extern "C" {
@@ -409,7 +479,8 @@ const char* nsgc_status_string(int status) {
     case NSGC_ERR_NO_MEMORY: return "device workspace allocation failed";
     case NSGC_ERR_HIP: return "HIP runtime error";
     case NSGC_ERR_INTERNAL: return "internal error";
-    case NSGC_ERR_CAPTURING: return "allocation needed while the stream is being captured";
+    case NSGC_ERR_CAPTURING: return "called on a stream that is being captured";
+    case NSGC_ERR_TOO_LARGE: return "batch does not fit the fixed scratch of nsgc_window_stats_noalloc";
     default: return "unknown status";
   }
 }

@@ -37,9 +37,19 @@ def test_library_exports_every_declared_symbol():
         assert name in exported, name
 
 
+def test_noalloc_limits_match_the_header():
+    text = open(HEADER).read()
+    scratch = re.search(r"#define NSGC_NOALLOC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", text)
+    plan = re.search(r"#define NSGC_NOALLOC_PLAN_BYTES \((\d+)ull << (\d+)\)", text)
+    assert scratch and plan
+    assert int(scratch[1]) << int(scratch[2]) == nsgc.NOALLOC_SCRATCH_BYTES
+    assert int(plan[1]) << int(plan[2]) == nsgc.NOALLOC_PLAN_BYTES
+    assert nsgc.NOALLOC_PLAN_BYTES % 256 == 0 < nsgc.NOALLOC_PLAN_BYTES < nsgc.NOALLOC_SCRATCH_BYTES
+
+
 def test_status_strings():
     lib = nsgc.library()
-    for code in range(-6, 1):
+    for code in range(-7, 1):
         assert lib.nsgc_status_string(code)
     assert lib.nsgc_status_string(-99) == b"unknown status"
 
@@ -50,7 +60,8 @@ def _call(fn, src, dst, off, w, out):
               ctypes.c_void_p(out), ctypes.c_void_p(0))
 
 
-@pytest.mark.parametrize("entry", ["nsgc_window_stats", "nsgc_window_stats_plain"])
+@pytest.mark.parametrize("entry", ["nsgc_window_stats", "nsgc_window_stats_plain",
+                                   "nsgc_window_stats_noalloc"])
 def test_invalid_arguments_rejected_before_any_device_work(entry):
     fn = getattr(nsgc.library(), entry)
     off = np.array([0, 4, 8], np.int64)
