@@ -60,6 +60,10 @@ def _load():
         lib.nsgc_oracle_window_stats.argtypes = [
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
             ctypes.c_void_p, ctypes.c_int]
+        lib.nsgc_oracle_unique_ips.restype = ctypes.c_int
+        lib.nsgc_oracle_unique_ips.argtypes = [
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+            ctypes.c_void_p, ctypes.c_int]
         lib.nsgc_oracle_window_entities.restype = ctypes.c_int
         lib.nsgc_oracle_window_entities.argtypes = [
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64] + [
@@ -93,9 +97,31 @@ def window_stats(src, dst, offsets, threads: int = 1) -> np.ndarray:
     return out
 
 
+def unique_ips(src, dst, offsets, threads: int = 1) -> np.ndarray:
+    """Globally unique IP addresses per window, |{src} U {dst}| (Section IV,
+    "Graph Analytics" paragraph), as a (W,) uint64 array."""
+    lib = _load()
+    src = np.ascontiguousarray(src, dtype=np.uint32)
+    dst = np.ascontiguousarray(dst, dtype=np.uint32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    w = len(offsets) - 1
+    out = np.zeros(max(w, 0), dtype=np.uint64)
+    if w <= 0:
+        return out
+    if offsets[-1] > src.size or offsets[-1] > dst.size:
+        raise ValueError("offsets run past the packet arrays")
+    rc = lib.nsgc_oracle_unique_ips(src.ctypes.data, dst.ctypes.data, offsets.ctypes.data, w,
+                                    out.ctypes.data, int(threads))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments (offsets must be >= 0 and "
+                         "non-decreasing)")
+    return out
+
+
 def window_entities(src, dst, begin: int = 0, end: int | None = None) -> dict:
     """Sorted per-entity vectors of one window: A as (key, count), the rows
-    (s, r(s), f(s)) and the columns (d, c(d), g(d))."""
+    (s, r(s), f(s)), the columns (d, c(d), g(d)) and the number of globally
+    unique IP addresses |{s} U {d}|."""
     lib = _load()
     src = np.ascontiguousarray(src, dtype=np.uint32)
     dst = np.ascontiguousarray(dst, dtype=np.uint32)
@@ -117,4 +143,6 @@ def window_entities(src, dst, begin: int = 0, end: int | None = None) -> dict:
         "link_keys": lk[:a], "link_counts": lc[:a],
         "row_ids": ri[:b], "row_packets": rp[:b], "row_links": rl[:b],
         "col_ids": ci[:c], "col_packets": cp[:c], "col_links": cl[:c],
+        "unique_ips": int(unique_ips(src[begin:end], dst[begin:end],
+                                     np.array([0, end - begin], np.int64))[0]),
     }

@@ -38,6 +38,7 @@
 #include <atomic>
 #include <cstdint>
 #include <map>
+#include <set>
 #include <thread>
 #include <utility>
 #include <vector>
@@ -91,6 +92,18 @@ void one_window(const uint32_t* src, const uint32_t* dst, int64_t begin, int64_t
   out[8] = max_g;
 }
 
+// Globally unique IP addresses of one window (Section IV, "Graph Analytics"
+// paragraph: the unique values of each column with the values common to both
+// counted once): the size of the union of the source and destination sets.
+uint64_t unique_ips(const uint32_t* src, const uint32_t* dst, int64_t begin, int64_t end) {
+  std::set<uint32_t> ips;
+  for (int64_t i = begin; i < end; ++i) {
+    ips.insert(src[i]);
+    ips.insert(dst[i]);
+  }
+  return static_cast<uint64_t>(ips.size());
+}
+
 }  // namespace
 
 extern "C" {
@@ -125,6 +138,38 @@ int nsgc_oracle_window_stats(const uint32_t* src, const uint32_t* dst,
     }
   };
   const int n = static_cast<int>(std::min<int64_t>(threads, num_windows));
+  std::vector<std::thread> pool;
+  pool.reserve(n);
+  for (int t = 0; t < n; ++t) pool.emplace_back(worker);
+  for (auto& t : pool) t.join();
+  return 0;
+}
+
+// |{sources} U {destinations}| per window for windows [offsets[w], offsets[w+1]):
+// out[w] receives the count.  Same argument rules and return values as
+// nsgc_oracle_window_stats.
+int nsgc_oracle_unique_ips(const uint32_t* src, const uint32_t* dst, const int64_t* offsets,
+                           int64_t num_windows, uint64_t* out, int threads) {
+  if (num_windows < 0) return -1;
+  if (num_windows == 0) return 0;
+  if (!offsets || !out) return -1;
+  if (offsets[0] < 0) return -1;
+  for (int64_t w = 0; w < num_windows; ++w)
+    if (offsets[w + 1] < offsets[w]) return -1;
+  if (offsets[num_windows] > offsets[0] && (!src || !dst)) return -1;
+  std::atomic<int64_t> next(0);
+  auto worker = [&]() {
+    for (;;) {
+      const int64_t w = next.fetch_add(1);
+      if (w >= num_windows) break;
+      out[w] = unique_ips(src, dst, offsets[w], offsets[w + 1]);
+    }
+  };
+  const int n = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(threads, num_windows)));
+  if (n == 1) {
+    worker();
+    return 0;
+  }
   std::vector<std::thread> pool;
   pool.reserve(n);
   for (int t = 0; t < n; ++t) pool.emplace_back(worker);

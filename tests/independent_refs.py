@@ -63,3 +63,17 @@ def numpy_unique(src, dst) -> np.ndarray:
     nd, cmax, gmax = grouped(link_dst)
     return np.array([int(counts.sum()), links.size, int(counts.max()), ns, rmax, fmax,
                      nd, cmax, gmax], dtype=np.uint64)
+
+
+def brute_force_unique_ips(src, dst) -> int:
+    """|{src} U {dst}| by pairwise comparison: an address counts where it
+    first occurs in the sequence src[0], dst[0], src[1], dst[1], ..."""
+    seq = np.empty(2 * len(src), dtype=np.int64)
+    seq[0::2] = np.asarray(src, dtype=np.int64)
+    seq[1::2] = np.asarray(dst, dtype=np.int64)
+    n = seq.size
+    if n == 0:
+        return 0
+    eq = seq[:, None] == seq[None, :]
+    earlier = np.tril(np.ones((n, n), dtype=bool), -1)
+    return int((~np.any(eq & earlier, axis=1)).sum())
