@@ -186,7 +186,11 @@ typedef struct nsgc_tune_class {
   int32_t link_target;      /* packets per link bucket (sets the bucket count) */
   int32_t row_target;       /* packets per row bucket */
   int32_t col_target;       /* packets per column bucket */
-  int32_t reserved;
+  int32_t wave_target;      /* > 0: link aggregation takes one wavefront per link
+                               bucket of about this many packets (64..2048), for
+                               windows whose row and column bucket counts stay
+                               within 256 and whose link buckets within the cap;
+                               0: one workgroup per bucket of link_target packets */
 } nsgc_tune_class;
 
 typedef struct nsgc_tune {

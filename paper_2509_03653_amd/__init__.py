@@ -85,7 +85,7 @@ class NsgcError(RuntimeError):
 
 class TuneClass(ctypes.Structure):
     _fields_ = [("link_target", ctypes.c_int32), ("row_target", ctypes.c_int32),
-                ("col_target", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("col_target", ctypes.c_int32), ("wave_target", ctypes.c_int32)]
 
 
 class Tune(ctypes.Structure):
@@ -108,7 +108,8 @@ class Tune(ctypes.Structure):
 
     def to_dict(self) -> dict:
         d = {k: int(getattr(self, k)) for k in self.SCALARS}
-        d["cls"] = [[int(c.link_target), int(c.row_target), int(c.col_target)] for c in self.cls]
+        d["cls"] = [[int(c.link_target), int(c.row_target), int(c.col_target), int(c.wave_target)]
+                    for c in self.cls]
         return d
 
     @classmethod
@@ -119,7 +120,10 @@ class Tune(ctypes.Structure):
             if k in d:
                 setattr(t, k, int(d[k]))
         for i, row in enumerate(d.get("cls", [])):
-            t.cls[i].link_target, t.cls[i].row_target, t.cls[i].col_target = (int(x) for x in row)
+            # [link, row, col] or [link, row, col, wave]; a missing wave target keeps its default
+            t.cls[i].link_target, t.cls[i].row_target, t.cls[i].col_target = (int(x) for x in row[:3])
+            if len(row) > 3:
+                t.cls[i].wave_target = int(row[3])
         return t
 
 

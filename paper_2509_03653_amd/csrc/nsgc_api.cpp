@@ -23,12 +23,15 @@ hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t
                             uint32_t grid, size_t lds, hipStream_t s);
 hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_buckets, uint32_t grid,
                         size_t lds, hipStream_t s);
+hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
 hipError_t launch_order(const nsgc_dev_plan* P, hipStream_t s);
+hipError_t launch_finish(const nsgc_dev_plan* P, uint32_t grid, hipStream_t s);
 hipError_t launch_rowcol(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
 size_t lds_small_bytes(uint32_t slots_log2);
-size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2);
+size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2, uint32_t max_rc_buckets);
 size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_rc_buckets);
 size_t lds_rc_bytes(uint32_t slots_log2);
+size_t lds_links_wave_bytes();
 hipError_t allow_large_lds(size_t bytes);
 hipError_t resident_blocks(int which, uint32_t tile_log2, size_t lds, int* blocks);
 }  // namespace nsgc
@@ -184,9 +187,9 @@ int take_stage(Slot* sl, size_t need, hipStream_t s, int* idx) {
 }
 
 struct Launch {
-  uint32_t grid_small, grid_part, grid_link, grid_rc;  // persistent grid of each kernel
+  uint32_t grid_small, grid_part, grid_link, grid_rc, grid_linkw, grid_finish;  // persistent grids
   bool combine;                                        // phase-B emission combines per id
-  size_t lds_small, lds_part, lds_link, lds_rc;
+  size_t lds_small, lds_part, lds_link, lds_rc, lds_linkw;
   uint32_t max_link_buckets, max_rc_buckets;
 };
 
@@ -212,10 +215,12 @@ int launch_params(DevCtx* c, const nsgc_tune& t, Launch* out) {
       uint32_t(std::max(ceil_log2(uint64_t(std::max(t.small_max, 1)) * 2), 6));
   const uint32_t tile = uint32_t(t.tile_log2);
   L.lds_small = lds_small_bytes(small_log2);
-  L.lds_part = lds_part_bytes(L.max_link_buckets, tile);
+  L.lds_part = lds_part_bytes(L.max_link_buckets, tile, L.max_rc_buckets);
   L.lds_link = lds_link_bytes(uint32_t(t.link_slots_log2), L.max_rc_buckets);
   L.lds_rc = lds_rc_bytes(uint32_t(t.rc_slots_log2));
-  const size_t m = std::max(std::max(L.lds_small, L.lds_part), std::max(L.lds_link, L.lds_rc));
+  L.lds_linkw = lds_links_wave_bytes();
+  const size_t m = std::max(std::max(std::max(L.lds_small, L.lds_part), std::max(L.lds_link, L.lds_rc)),
+                            L.lds_linkw);
   if (m > c->lds_limit) return NSGC_ERR_INVALID_ARG;
   int rc;
   const int want = t.blocks_per_cu;
@@ -225,13 +230,20 @@ int launch_params(DevCtx* c, const nsgc_tune& t, Launch* out) {
   if ((rc = resident_cap(c, L.combine ? 4 : 2, tile, L.lds_link, want, &L.grid_link)) != NSGC_OK)
     return rc;
   if ((rc = resident_cap(c, 3, tile, L.lds_rc, want, &L.grid_rc)) != NSGC_OK) return rc;
+  // the wavefront kernel runs four small workgroups per CU for every one of
+  // the workgroup kernels' 512-thread workgroups
+  if ((rc = resident_cap(c, 5, tile, L.lds_linkw, 4 * want, &L.grid_linkw)) != NSGC_OK) return rc;
+  L.grid_finish = uint32_t(c->cus) * 4;
   *out = L;
   return NSGC_OK;
 }
 
-// Which kernels a plan needs: bit 0 the small-window kernel, bit 1 phases A-C.
+// Which kernels a plan needs: bit 0 the small-window kernel, bit 1 phases A
+// and C, bit 2 phase B by workgroups, bit 3 phase B by wavefronts.
+constexpr int kVariants = 16;
 int plan_variant(const HostPlan& hp) {
-  return (hp.small.empty() ? 0 : 1) | (hp.win.empty() ? 0 : 2);
+  return (hp.small.empty() ? 0 : 1) | (hp.win.empty() ? 0 : 2) | (hp.itemsBb ? 4 : 0) |
+         (hp.itemsBw ? 8 : 0);
 }
 
 // Enqueue the kernels of one uploaded plan.  With `fixed_grid` (graph
@@ -245,6 +257,8 @@ int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch
   auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
   const bool small = fixed_grid ? (variant & 1) != 0 : !hp.small.empty();
   const bool part = fixed_grid ? (variant & 2) != 0 : !hp.win.empty();
+  const bool linkb = fixed_grid ? (variant & 4) != 0 : hp.itemsBb > 0;
+  const bool linkw = fixed_grid ? (variant & 8) != 0 : hp.itemsBw > 0;
   NSGC_HIP(mark(0));
   if (small)
     NSGC_HIP(launch_small(dplan, grid(uint32_t(hp.small.size()), L.grid_small), L.lds_small, s));
@@ -253,12 +267,15 @@ int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch
     NSGC_HIP(launch_partition(dplan, tile_log2, L.max_link_buckets, grid(hp.itemsA, L.grid_part),
                               L.lds_part, s));
   NSGC_HIP(mark(2));
-  if (part)
-    NSGC_HIP(launch_links(dplan, L.combine, L.max_rc_buckets, grid(hp.itemsB, L.grid_link),
+  if (linkw)
+    NSGC_HIP(launch_links_wave(dplan, grid((hp.itemsBw + 3) / 4, L.grid_linkw), L.lds_linkw, s));
+  if (linkb)
+    NSGC_HIP(launch_links(dplan, L.combine, L.max_rc_buckets, grid(hp.itemsBb, L.grid_link),
                           L.lds_link, s));
   NSGC_HIP(mark(3));
   if (part) NSGC_HIP(launch_order(dplan, s));
   if (part) NSGC_HIP(launch_rowcol(dplan, grid(hp.itemsC, L.grid_rc), L.lds_rc, s));
+  if (part) NSGC_HIP(launch_finish(dplan, grid(uint32_t(hp.win.size()), L.grid_finish), s));
   NSGC_HIP(mark(4));
   return NSGC_OK;
 }
@@ -315,6 +332,7 @@ size_t workspace_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune
   int lt = 1 << 30, rt = 1 << 30;
   for (int k = 0; k <= 32; ++k) {
     lt = std::min(lt, t.cls[k].link_target);
+    if (t.cls[k].wave_target > 0) lt = std::min(lt, t.cls[k].wave_target);
     rt = std::min(rt, std::min(t.cls[k].row_target, t.cls[k].col_target));
   }
   const uint64_t MB = uint64_t(1) << t.max_link_buckets_log2;
@@ -326,7 +344,9 @@ size_t workspace_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune
   const uint64_t lbmeta = (std::min<uint64_t>(bmax * W, 2 * P / uint64_t(lt) + W)) * (2 * rmax + 3);
   // phase-C items: R_w + C_w < 4 n_w / rt + 4 per window, at most 2 * MRC
   const uint64_t items = std::min<uint64_t>(4 * P / uint64_t(rt) + 4 * W, 2 * W * MRC);
-  return size_t(P * 24 + (tilemeta + lbmeta + 2 * items) * 4 + 8 * 256);
+  // bucket totals: 16 B per phase-B and per phase-C item
+  const uint64_t bitems = std::min<uint64_t>(2 * P / uint64_t(lt) + 2 * W, W * MB);
+  return size_t(P * 24 + (tilemeta + lbmeta + 2 * items) * 4 + (bitems + items) * 16 + 10 * 256);
 }
 
 // The batched form (caller holds g_mu, arguments validated, num_windows > 0).
@@ -682,8 +702,8 @@ struct nsgc_graph {
     char* plan_dev = nullptr;
     size_t plan_cap = 0;
     char* stage = nullptr;
-    hipGraph_t graph[4] = {};     // indexed by plan variant (see plan_variant)
-    hipGraphExec_t exec[4] = {};
+    hipGraph_t graph[kVariants] = {};     // indexed by plan variant (see plan_variant)
+    hipGraphExec_t exec[kVariants] = {};
     hipEvent_t done = nullptr;
     hipStream_t stream = nullptr;  // stream of the last launch
     bool used = false;
@@ -721,7 +741,7 @@ int capture_instance(nsgc_graph* g, nsgc_graph::Inst& in, int variant) {
 void destroy_graph(nsgc_graph* g) {
   for (auto& in : g->inst) {
     if (in.done) (void)hipEventSynchronize(in.done);
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < kVariants; ++v) {
       if (in.exec[v]) (void)hipGraphExecDestroy(in.exec[v]);
       if (in.graph[v]) (void)hipGraphDestroy(in.graph[v]);
     }

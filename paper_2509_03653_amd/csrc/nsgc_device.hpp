@@ -70,17 +70,13 @@ __device__ __forceinline__ T sload_words(const T* p) {
 }
 
 // ---- hashing: invertible xorshift / odd-multiply mixers ------------------
-// Bijections, so the bucket, sweep and slot bits taken from one mix of a key
-// can always be refined until a group holds a single key.
-
-__device__ __forceinline__ u64 link_hash(u64 x) {
-  x ^= x >> 32;
-  x *= 0x22781625FEAE7023ull;
-  x ^= x >> 29;
-  x *= 0xFDEAD8A9C227D53Dull;
-  x ^= x >> 32;
-  return x;
-}
+// row_hash and col_hash are bijections on 32 bits.  Every kernel works on
+// addresses in this hashed form: a source s is represented by row_hash(s), a
+// destination d by col_hash(d), and a link (s, d) by the 64-bit key
+// row_hash(s) << 32 | col_hash(d).  Equality is preserved both ways, so
+// counting distinct hashed values counts distinct addresses or links, and the
+// values are already mixed: bucket, sweep and slot bits are read off them
+// without hashing again in the later phases.
 
 __device__ __forceinline__ uint32_t row_hash(uint32_t x) {
   x ^= 0x421E9A93u;
@@ -100,6 +96,25 @@ __device__ __forceinline__ uint32_t col_hash(uint32_t x) {
   x *= 0xA84F7BAFu;
   x ^= x >> 16;
   return x;
+}
+
+__device__ __forceinline__ uint32_t rotl32(uint32_t x, uint32_t r) {
+  return (x << r) | (x >> (32u - r));
+}
+
+// The hashed link key of packet (s, d).
+__device__ __forceinline__ u64 link_key(uint32_t s, uint32_t d) {
+  return (u64(row_hash(s)) << 32) | col_hash(d);
+}
+
+// Position bits of a hashed link key: the link bucket is the top bits, the
+// overflow sweeps take the bits that follow, and the low 32 bits pick the
+// LDS table slot.  Both halves of the key are already mixed, so crossing them
+// with rotations is enough to make every bit depend on source and
+// destination (a star or a reverse star still spreads over all buckets).
+__device__ __forceinline__ u64 link_pos(u64 k) {
+  const uint32_t r = uint32_t(k >> 32), c = uint32_t(k);
+  return (u64(r ^ rotl32(c, 13)) << 32) | (c ^ rotl32(r, 7));
 }
 
 // top k bits (k may be 0)
@@ -405,6 +420,9 @@ __device__ __forceinline__ uint32_t owner_of_wave(const NSGC_GLOBAL uint32_t* pr
   return lo;
 }
 
+// End marker of the work queues (no item has this index).
+constexpr uint32_t NO_ITEM = 0xFFFFFFFFu;
+
 // Dynamic work queue, so that uneven items (heavy buckets, windows of very
 // different sizes) spread over the grid.  Device-scope atomics on one
 // address are serialised (tens of ns each), which a queue of thousands of
@@ -422,7 +440,7 @@ __device__ __forceinline__ uint32_t owner_of_wave(const NSGC_GLOBAL uint32_t* pr
 //
 // Loop shape (one barrier per item for the queue, shared with the item's
 // last one; the item body must contain a barrier before stage_next):
-//   for (item = q.first(items); item < items; item = q.read()) {
+//   for (item = q.first(items); item != NO_ITEM; item = q.read()) {
 //     ...;  q.stage_next(items);  __syncthreads();
 //   }
 struct ItemQueue {
@@ -448,8 +466,10 @@ struct ItemQueue {
         __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return base + step * t;
   }
+  // The item at queue position pos, or NO_ITEM past the end (a mapped item
+  // index may exceed the number of positions, so `items` cannot be the end).
   __device__ __forceinline__ uint32_t item_at(uint32_t pos, uint32_t items) const {
-    return pos < items ? (map ? map[pos] : pos) : items;
+    return pos < items ? (map ? map[pos] : pos) : NO_ITEM;
   }
   __device__ __forceinline__ uint32_t first(uint32_t items) {
     if (threadIdx.x == 0) {
@@ -465,6 +485,14 @@ struct ItemQueue {
     if (threadIdx.x == 0 && !resolved) {
       pending_item = item_at(pending, items);
       resolved = true;
+    }
+  }
+  // Thread 0 writes the next item (or NO_ITEM when there is none) to the LDS
+  // word *at; visible after the caller's next barrier.
+  __device__ __forceinline__ void announce(uint32_t* at, uint32_t items) {
+    if (threadIdx.x == 0) {
+      resolve(items);
+      *at = pending_item;
     }
   }
   // Thread 0 publishes the next item; visible after the caller's barrier.

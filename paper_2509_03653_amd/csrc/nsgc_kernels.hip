@@ -97,6 +97,7 @@ static_assert(LK * NSGC_BLOCK <= ENT_LMAX, "a bucket's links fit the link field"
 
 // Entries needed for an (id, links, packets) triple (1 <= links <= packets).
 __device__ __forceinline__ uint32_t entry_parts(uint32_t packets, uint32_t links) {
+  if (packets <= ENT_PMAX && links <= ENT_LMAX) return 1u;
   const uint32_t a = packets / ENT_PMAX + (packets % ENT_PMAX != 0);
   const uint32_t b = links / ENT_LMAX + (links % ENT_LMAX != 0);
   return max(max(a, b), 1u);
@@ -122,8 +123,9 @@ __device__ __forceinline__ void write_entry(NSGC_GLOBAL u64* e, uint32_t at, uin
 // ---------------------------------------------------------------------------
 // Tier "small": one workgroup per window, everything in LDS.
 //
-// Per packet: find-or-insert the link key (the inserting lane learns that the
-// link is new) and add one packet to it; add one packet to the source's row
+// Per packet, in hashed identities (link_key): find-or-insert the link key
+// (the inserting lane learns that the link is new) and add one packet to it;
+// add one packet to the source's row
 // and, if the link is new, one link to its fan-out; the same for the
 // destination's column.  Tables hold 2^k >= 2 n slots.
 // ---------------------------------------------------------------------------
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
 
   const uint32_t items = P->num_small;
   ItemQueue q(gptr(&P->queue[0][0]), misc + 7, NSGC_QCLASSES);
-  for (uint32_t item = q.first(items); item < items; item = q.read()) {
+  for (uint32_t item = q.first(items); item != NO_ITEM; item = q.read()) {
     const nsgc_small_desc D = gload(P->small + item);
     for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
       lk[i] = EMPTY64;
@@ -182,9 +184,11 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
         d[u] = ok[u] ? dst[j] : 0u;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < U; ++u) {   // hashed identities (see link_key)
+        s[u] = row_hash(s[u]);
+        d[u] = col_hash(d[u]);
         key[u] = (u64(s[u]) << 32) | d[u];
-        h[u] = uint32_t(link_hash(key[u]));
+        h[u] = uint32_t(link_pos(key[u]));
         // the key equal to the empty marker is counted outside the table
         tab[u] = ok[u] && key[u] != EMPTY64;
       }
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         rt[u] = ok[u] && s[u] != EMPTY32;
-        h[u] = row_hash(s[u]);
+        h[u] = s[u];
       }
       if (!cas_insert<U>(rk, S - 1, s, h, rt, slot, tab, S + 1)) lds_store(&misc[6], 1);
 #pragma unroll
@@ -219,7 +223,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         rt[u] = ok[u] && d[u] != EMPTY32;
-        h[u] = col_hash(d[u]);
+        h[u] = d[u];
       }
       if (!cas_insert<U>(ck, S - 1, d, h, rt, slot, tab, S + 1)) lds_store(&misc[6], 1);
 #pragma unroll
@@ -278,7 +282,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
 // phase-C item sizes that phase B sums when the plan orders phase C.
 // ---------------------------------------------------------------------------
 
-size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2) {
+size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2, uint32_t max_rc_buckets) {
+  (void)max_rc_buckets;   // the row/column sample shares the staging area
   return align16((max_link_buckets + 1) * 4) + align16((size_t(1) << tile_log2) * 8) + 256;
 }
 
@@ -291,23 +296,28 @@ __global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restric
   uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
   u64* stage = reinterpret_cast<u64*>(smem + align16((max_link_buckets + 1) * 4));
   uint32_t* red = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(stage) + T * 8);
-  // clear the phase-C item sizes that phase B accumulates for the ordering
-  if (P->order_items) {
-    NSGC_GLOBAL uint32_t* sz = gptr(P->rcsize);
-    const uint32_t nc = P->itemsC;
-    for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < nc; i += gridDim.x * NT)
-      sz[i] = 0;
-  }
+  // packets per row and column bucket of a window's first tile; in the staging
+  // area, which is free until the bucket scan's barriers
+  uint32_t* rch = reinterpret_cast<uint32_t*>(stage);
   const uint32_t items = P->itemsA;
   for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
     const uint32_t wi = owner_of_wave(gptr(P->prefA), P->num_part, item);
     const nsgc_win_desc W = gload(P->win + wi);
     const uint32_t t = item - gptr(P->prefA)[wi];
-    const uint32_t B = 1u << W.logB;
+    const uint32_t B = 1u << W.logB, R = 1u << W.logR, C = 1u << W.logC;
     const uint32_t tbeg = t * T;
     const uint32_t len = min(T, W.n - tbeg);
+    // The first tile of a window also counts its packets per row and column
+    // bucket: the phase-C item sizes by which k_order starts large items first
+    // (a sample, so only the order depends on it).
+    const bool sample = t == 0 && P->order_items && R + C <= 2 * T;
+    if (t == 0 && P->order_items && !sample) {   // too many buckets to sample: equal sizes
+      NSGC_GLOBAL uint32_t* sz = gptr(P->rcsize) + gptr(P->prefC)[wi];
+      for (uint32_t i = threadIdx.x; i < R + C; i += NT) sz[i] = 1;
+    }
     for (uint32_t i = threadIdx.x; i < B; i += NT) hist[i] = 0;
-    if (t == 0 && threadIdx.x < 9) gptr(P->out)[u64(W.out_index) * 9 + threadIdx.x] = 0;
+    if (sample)
+      for (uint32_t i = threadIdx.x; i < R + C; i += NT) rch[i] = 0;
     __syncthreads();
 
     const uint64_t gbeg = uint64_t(W.in_begin) + tbeg;
@@ -325,10 +335,10 @@ __global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restric
         const uint32_t idx = (k * NT + threadIdx.x) * 4;
         const v4u32 s4 = *(const NSGC_GLOBAL v4u32*)(src + idx);
         const v4u32 d4 = *(const NSGC_GLOBAL v4u32*)(dst + idx);
-        key[4 * k + 0] = (u64(s4.x) << 32) | d4.x;
-        key[4 * k + 1] = (u64(s4.y) << 32) | d4.y;
-        key[4 * k + 2] = (u64(s4.z) << 32) | d4.z;
-        key[4 * k + 3] = (u64(s4.w) << 32) | d4.w;
+        key[4 * k + 0] = link_key(s4.x, d4.x);
+        key[4 * k + 1] = link_key(s4.y, d4.y);
+        key[4 * k + 2] = link_key(s4.z, d4.z);
+        key[4 * k + 3] = link_key(s4.w, d4.w);
         ok[4 * k + 0] = ok[4 * k + 1] = ok[4 * k + 2] = ok[4 * k + 3] = true;
       }
     } else {
@@ -336,17 +346,30 @@ __global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restric
       for (int k = 0; k < PER; ++k) {
         const uint32_t idx = k * NT + threadIdx.x;
         ok[k] = idx < len;
-        key[k] = ok[k] ? ((u64(src[idx]) << 32) | dst[idx]) : 0ull;
+        key[k] = ok[k] ? link_key(src[idx], dst[idx]) : 0ull;
       }
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       if (ok[k]) {
-        const uint32_t bk = top64(link_hash(key[k]), W.logB);
+        const uint32_t bk = top64(link_pos(key[k]), W.logB);
         br[k] = (lds_add(&hist[bk], 1) << 12) | bk;
       }
     }
+    if (sample) {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        if (ok[k]) {
+          lds_add(&rch[top32(uint32_t(key[k] >> 32), W.logR)], 1);
+          lds_add(&rch[R + top32(uint32_t(key[k]), W.logC)], 1);
+        }
+      }
+    }
     __syncthreads();
+    if (sample) {
+      NSGC_GLOBAL uint32_t* sz = gptr(P->rcsize) + gptr(P->prefC)[wi];
+      for (uint32_t i = threadIdx.x; i < R + C; i += NT) sz[i] = rch[i];
+    }
     block_exclusive_scan<NT>(hist, B, red);
 #pragma unroll
     for (int k = 0; k < PER; ++k)
@@ -418,8 +441,21 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
 // the segment-by-segment walk's chunks (its search costs part of a chunk).
 constexpr uint32_t PACK_NUM = 7, PACK_DEN = 8;
 
-template <int MAXU, class SegFn, class BatchFn>
-__device__ __forceinline__ void gather_by_wave(uint32_t nseg, SegFn seg, BatchFn fn) {
+// This lane's segment of the first group (segments w + WAVES * lane), when
+// the caller loaded it beforehand (zero length where there is none).
+struct SegPre {
+  u64 base;
+  uint32_t len;
+};
+
+struct NoTail {
+  __device__ void operator()() const {}
+};
+
+// `tail()` runs in every thread just before the final barrier.
+template <int MAXU, class SegFn, class BatchFn, class Tail = NoTail>
+__device__ __forceinline__ void gather_by_wave(uint32_t nseg, SegFn seg, BatchFn fn,
+                                               const SegPre* pre = nullptr, Tail tail = Tail()) {
   const uint32_t w = uniform(threadIdx.x >> 6), lane = lane_id();
   constexpr uint32_t GROUP = 64u * uint32_t(WAVES);
   constexpr int PACKU = MAXU < 4 ? MAXU : 4;
@@ -427,7 +463,12 @@ __device__ __forceinline__ void gather_by_wave(uint32_t nseg, SegFn seg, BatchFn
     const uint32_t si = g0 + w + uint32_t(WAVES) * lane;   // this lane's segment
     u64 mybase = 0;
     uint32_t mylen = 0;
-    if (si < nseg) seg(si, mybase, mylen);
+    if (g0 == 0 && pre) {
+      mybase = pre->base;
+      mylen = pre->len;
+    } else if (si < nseg) {
+      seg(si, mybase, mylen);
+    }
     const uint32_t nk = uniform(g0 + w < nseg ? min(64u, (nseg - g0 - w + WAVES - 1) / WAVES) : 0u);
     const uint32_t chunks = uniform(wave_sum((mylen + 63u) >> 6));   // segment by segment
     const uint32_t elems = uniform(wave_sum(mylen));
@@ -485,6 +526,7 @@ __device__ __forceinline__ void gather_by_wave(uint32_t nseg, SegFn seg, BatchFn
       fn(pos, ok);
     });
   }
+  tail();
   __syncthreads();
 }
 
@@ -552,9 +594,35 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
   if (threadIdx.x == 0) misc[5] = 0;
 
   const uint32_t T = 1u << P->tile_log2;
-  const uint32_t items = P->itemsB;
-  ItemQueue q(gptr(&P->queue[1][0]), misc + 7, LINK_QCLASSES);
-  for (uint32_t item = q.first(items); item < items; item = q.read()) {
+  const uint32_t items = P->itemsBb;
+  const NSGC_GLOBAL uint32_t* map = P->mapBb ? gptr(P->mapBb) : nullptr;
+  const uint32_t wave = uniform(threadIdx.x >> 6), lane = lane_id();
+  // The first group of an item's segments: lane l of wave w holds tile
+  // w + WAVES * l (its start s0 in the bucket and the segment).  Loaded for
+  // the next item while the current one finishes, so that an item's gather
+  // starts with its key loads instead of a chain of metadata loads.
+  auto load_first = [&](uint32_t it, SegPre& pre, uint32_t& s0) {
+    const uint32_t wi = sload(P->itemwinB + it);
+    const nsgc_win_desc W = sload_words(P->win + wi);
+    const uint32_t b = it - sload(P->prefB + wi);
+    const NSGC_GLOBAL uint32_t* t0 = gptr(P->tilemeta) + W.tilemeta + u64(b) * W.ntiles;
+    const uint32_t t = wave + uint32_t(WAVES) * lane;
+    pre.base = 0;
+    pre.len = 0;
+    s0 = 0;
+    if (t < W.ntiles) {
+      const uint32_t a = t0[t], c = t0[t + W.ntiles];
+      s0 = a;
+      pre.base = u64(t) * T + a;
+      pre.len = c - a;
+    }
+  };
+  SegPre next_pre = {0, 0};
+  uint32_t next_s0 = 0;
+  bool have_next = false;
+
+  ItemQueue q(gptr(&P->queue[1][0]), misc + 7, LINK_QCLASSES, map);
+  for (uint32_t item = q.first(items); item != NO_ITEM; item = q.read()) {
     const uint32_t it = uniform(item);
     const uint32_t wi = sload(P->itemwinB + it);
     const nsgc_win_desc W = sload_words(P->win + wi);
@@ -566,11 +634,24 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
     const NSGC_GLOBAL uint32_t* tm1 = tm0 + nt;                                      // bucket b+1
     NSGC_GLOBAL uint32_t* rec = gptr(P->lbmeta) + W.lbmeta;
 
+    SegPre pre;
+    uint32_t pre_s0;
+    if (have_next) {
+      pre = next_pre;
+      pre_s0 = next_s0;
+    } else {
+      load_first(it, pre, pre_s0);
+    }
+    have_next = false;
+    // thread 0 names the next item (read by all after the gather's barrier)
+    q.announce(&misc[6], items);
+    bool fetched = false;
+
     // The emission base of bucket b (packets of the window in link buckets
     // below b) is the sum of b's starts over the tiles: summed while the
     // first gather loads them.
     if (threadIdx.x == 0) misc[4] = 0;
-    uint32_t below = 0;
+    uint32_t below = pre_s0;
     bool base_pending = true;
 
     auto seg = [&](uint32_t t, u64& sbase, uint32_t& len) {
@@ -609,7 +690,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const u64 hh = link_hash(key[u]);
+          const u64 hh = link_pos(key[u]);
           h[u] = uint32_t(hh);
           ok[u] = okin[u] && !(logS && next64(hh, W.logB, logS) != sw);
           add[u] = 1;
@@ -644,7 +725,15 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
           const uint32_t at = wave_append(&misc[5], fresh[u]);
           if (fresh[u]) occ[at] = uint32_t(slot[u]);
         }
-      });
+      }, &pre);
+      if (!fetched) {   // the next item's first segments, loaded behind this item
+        fetched = true;
+        const uint32_t nx = uniform(misc[6]);
+        if (nx != NO_ITEM) {
+          load_first(nx, next_pre, next_s0);
+          have_next = true;
+        }
+      }
       if (base_pending) {   // visible after the barriers before any emission
         base_pending = false;
         below = wave_sum(below);
@@ -659,13 +748,13 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
         const uint32_t s = occ[i];
         const u64 key = tk[s];
         const uint32_t parts = entry_parts(tc[s], 1);
-        lds_add(&histR[top32(row_hash(uint32_t(key >> 32)), W.logR)], parts);
-        lds_add(&histC[top32(col_hash(uint32_t(key)), W.logC)], parts);
+        lds_add(&histR[top32(uint32_t(key >> 32), W.logR)], parts);
+        lds_add(&histC[top32(uint32_t(key), W.logC)], parts);
       }
       if (threadIdx.x == 0 && misc[1]) {
         const uint32_t parts = entry_parts(misc[1], 1);
-        lds_add(&histR[top32(row_hash(EMPTY32), W.logR)], parts);
-        lds_add(&histC[top32(col_hash(EMPTY32), W.logC)], parts);
+        lds_add(&histR[top32(EMPTY32, W.logR)], parts);
+        lds_add(&histC[top32(EMPTY32, W.logC)], parts);
       }
     };
     // Emission also empties the table (each listed slot once); the list
@@ -696,8 +785,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
         for (int u = 0; u < U; ++u) {
           if (ok[u]) {
             const uint32_t parts = entry_parts(cnt[u], 1);
-            ar[u] = lds_add(&histR[top32(row_hash(uint32_t(key[u] >> 32)), W.logR)], parts);
-            ac[u] = lds_add(&histC[top32(col_hash(uint32_t(key[u])), W.logC)], parts);
+            ar[u] = lds_add(&histR[top32(uint32_t(key[u] >> 32), W.logR)], parts);
+            ac[u] = lds_add(&histC[top32(uint32_t(key[u]), W.logC)], parts);
           }
         }
 #pragma unroll
@@ -712,9 +801,9 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
       if (threadIdx.x == 0 && misc[1]) {
         const uint32_t c = misc[1];
         const uint32_t parts = entry_parts(c, 1);
-        write_entry(er, lds_add(&histR[top32(row_hash(EMPTY32), W.logR)], parts), EMPTY32, c, 1,
+        write_entry(er, lds_add(&histR[top32(EMPTY32, W.logR)], parts), EMPTY32, c, 1,
                     parts);
-        write_entry(ec, lds_add(&histC[top32(col_hash(EMPTY32), W.logC)], parts), EMPTY32, c, 1,
+        write_entry(ec, lds_add(&histC[top32(EMPTY32, W.logC)], parts), EMPTY32, c, 1,
                     parts);
       }
       __syncthreads();
@@ -740,7 +829,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
       const uint32_t K = rows ? R : C;
       const uint32_t logK = rows ? W.logR : W.logC;
       auto ident = [&](u64 key) { return rows ? uint32_t(key >> 32) : uint32_t(key); };
-      auto bucket = [&](uint32_t x) { return top32(rows ? row_hash(x) : col_hash(x), logK); };
+      auto bucket = [&](uint32_t x) { return top32(x, logK); };
       for (uint32_t i = threadIdx.x; i <= K; i += NSGC_BLOCK) hist[i] = 0;
       if (threadIdx.x < 2) misc[2 + threadIdx.x] = 0;   // [2] distinct ids, [3] gave up
       __syncthreads();
@@ -751,7 +840,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           id[k] = ident(lkey[c + k]);
-          h[k] = rows ? row_hash(id[k]) : col_hash(id[k]);
+          h[k] = id[k];
           pk[k] = lcnt[c + k];
           ln[k] = 1;
           ok[k] = threadIdx.x + (c + k) * NSGC_BLOCK < nl && id[k] != EMPTY32;
@@ -848,15 +937,6 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
       for (uint32_t i = threadIdx.x; i <= R; i += NSGC_BLOCK) rec[B + u64(i) * B + b] = histR[i];
       for (uint32_t i = threadIdx.x; i <= C; i += NSGC_BLOCK)
         rec[B + u64(R + 1) * B + u64(i) * B + b] = histC[i];
-      // the counts also go to the phase-C items' sizes (a scheduling hint:
-      // large items are started first)
-      if (P->order_items) {
-        NSGC_GLOBAL uint32_t* sz = gptr(P->rcsize) + sload(P->prefC + wi);
-        for (uint32_t i = threadIdx.x; i < R + C; i += NSGC_BLOCK) {
-          const uint32_t v = i < R ? histR[i + 1] - histR[i] : histC[i - R + 1] - histC[i - R];
-          if (v) __hip_atomic_fetch_add(sz + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
     };
 
     // Attempt with 2^logS sweeps; any insert that gives up restarts the whole
@@ -942,19 +1022,326 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
     }
     if (threadIdx.x == 0) rec[b] = misc[4];
 
-    // bucket totals -> window statistics 0..2 (thread 0 holds them)
+    // the bucket's totals (thread 0 holds them), combined per window by k_finish
     uint32_t nlinks = links;
     block_sum2_max_to0(sum, nlinks, mx, st.red);
     if (threadIdx.x == 0) {
-      NSGC_GLOBAL u64* o = gptr(P->out) + u64(W.out_index) * 9;
-      if (abandoned)
-        __hip_atomic_fetch_or(o, NSGC_INVALID_BIT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      stat_add(o + 0, sum);
-      stat_add(o + 1, nlinks);
-      stat_max(o + 2, mx);
+      const v4u32 part = {sum, nlinks, mx, abandoned ? 1u : 0u};
+      gptr(reinterpret_cast<v4u32*>(P->partB))[it] = part;
     }
     q.stage_next(items);
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Phase B, one wavefront per link bucket (windows whose size class has a
+// wave target, see nsgc_tune_class): every wavefront of the grid takes link
+// buckets of about wave_target packets from its own work queue and
+// aggregates each in a private LDS table.  No wavefront waits for another, so
+// the latency of one wavefront's metadata loads, key gathers and LDS round
+// trips hides behind the work of the others (sixteen per compute unit); the
+// workgroup-wide barriers of k_links are gone.  The emission layout, the
+// overflow sweeps and the statistics are the same as k_links' per-link form.
+// ---------------------------------------------------------------------------
+
+constexpr int WAVE_NT = 256;                 // threads per workgroup
+constexpr int WAVE_WPB = WAVE_NT / 64;       // wavefronts per workgroup
+constexpr uint32_t WAVE_SLOTS = 1u << NSGC_WAVE_SLOTS_LOG2;
+constexpr uint32_t WAVE_HIST = NSGC_WAVE_MAX_RC + 1;   // counters per view
+static_assert(WAVE_SLOTS <= 65536, "slots are listed as 16-bit indices");
+
+// LDS of one wavefront: keys, counts, the occupied-slot list, the row and
+// column bucket counters.
+constexpr size_t WAVE_LDS = size_t(WAVE_SLOTS) * 8 + size_t(WAVE_SLOTS) * 4 +
+                            size_t(WAVE_SLOTS) * 2 + 2 * size_t(WAVE_HIST) * 4 + 64;
+
+size_t lds_links_wave_bytes() { return size_t(WAVE_WPB) * ((WAVE_LDS + 15) & ~size_t(15)); }
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Exclusive scan of a[0..n) in LDS by one wavefront (n <= 64 * 8); a[n]
+// receives the total.
+__device__ __forceinline__ void wave_exclusive_scan_lds(uint32_t* a, uint32_t n) {
+  const uint32_t lane = lane_id();
+  const uint32_t per = (n + 63u) >> 6;
+  const uint32_t beg = min(n, lane * per), end = min(n, beg + per);
+  uint32_t sum = 0;
+  for (uint32_t i = beg; i < end; ++i) sum += a[i];
+  const uint32_t incl = wave_inclusive_scan(sum);
+  uint32_t run = incl - sum;
+  for (uint32_t i = beg; i < end; ++i) {
+    const uint32_t x = a[i];
+    a[i] = run;
+    run += x;
+  }
+  if (lane == 63) a[n] = incl;
+  wave_fence();
+}
+
+// Work queue of single wavefronts: wavefront g of the grid takes item g
+// first, then items of its class (g mod K, K <= NSGC_QCLASSES) from a
+// per-class counter; lane 0 requests the next position while the current
+// item runs.
+struct WaveQueue {
+  NSGC_GLOBAL uint32_t* counter;
+  const NSGC_GLOBAL uint32_t* map;
+  uint32_t base, step, pending;
+  __device__ WaveQueue(NSGC_GLOBAL uint32_t* counters, uint32_t gwave, uint32_t gwaves,
+                       const NSGC_GLOBAL uint32_t* item_map)
+      : map(item_map), pending(0) {
+    step = min(uint32_t(NSGC_QCLASSES), gwaves);
+    const uint32_t c = gwave % step;
+    counter = counters + c * NSGC_QSTRIDE;
+    base = gwaves + c;
+  }
+  __device__ __forceinline__ uint32_t take() {
+    return base + step * __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __device__ __forceinline__ uint32_t item_at(uint32_t pos, uint32_t items) const {
+    return pos < items ? (map ? map[pos] : pos) : NO_ITEM;
+  }
+  // The first item (position gwave); lane 0 requests the next position.
+  __device__ __forceinline__ uint32_t first(uint32_t gwave, uint32_t items) {
+    if (lane_id() == 0) pending = gwave < items ? take() : items;
+    return uniform(item_at(gwave, items));
+  }
+  __device__ __forceinline__ uint32_t next(uint32_t items) {
+    uint32_t pos = 0;
+    if (lane_id() == 0) {
+      pos = pending;
+      pending = pos < items ? take() : items;
+    }
+    return uniform(item_at(uniform(pos), items));
+  }
+};
+
+__global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t w = uniform(threadIdx.x >> 6), lane = lane_id();
+  unsigned char* p = smem + size_t(w) * ((WAVE_LDS + 15) & ~size_t(15));
+  u64* tk = reinterpret_cast<u64*>(p);             p += size_t(WAVE_SLOTS) * 8;
+  uint32_t* tc = reinterpret_cast<uint32_t*>(p);   p += size_t(WAVE_SLOTS) * 4;
+  uint32_t* histR = reinterpret_cast<uint32_t*>(p);  p += size_t(WAVE_HIST) * 4;
+  uint32_t* histC = reinterpret_cast<uint32_t*>(p);  p += size_t(WAVE_HIST) * 4;
+  uint16_t* occ = reinterpret_cast<uint16_t*>(p);
+  constexpr uint32_t S = WAVE_SLOTS;
+
+  for (uint32_t i = lane; i < S; i += 64) {
+    tk[i] = EMPTY64;
+    tc[i] = 0;
+  }
+  wave_fence();
+
+  const uint32_t T = 1u << P->tile_log2;
+  const uint32_t items = P->itemsBw;
+  const uint32_t gwaves = gridDim.x * WAVE_WPB, gwave = blockIdx.x * WAVE_WPB + w;
+  WaveQueue q(gptr(&P->queue[3][0]), gwave, gwaves, P->mapBw ? gptr(P->mapBw) : nullptr);
+  for (uint32_t it = q.first(gwave, items); it != NO_ITEM; it = q.next(items)) {
+    const uint32_t wi = sload(P->itemwinB + it);
+    const nsgc_win_desc W = sload_words(P->win + wi);
+    const uint32_t b = it - sload(P->prefB + wi);
+    const uint32_t B = 1u << W.logB, R = 1u << W.logR, C = 1u << W.logC;
+    const uint32_t nt = W.ntiles;
+    const NSGC_GLOBAL u64* keys = gptr(P->keys) + W.ws;
+    const NSGC_GLOBAL uint32_t* tm0 = gptr(P->tilemeta) + W.tilemeta + u64(b) * nt;
+    NSGC_GLOBAL uint32_t* rec = gptr(P->lbmeta) + W.lbmeta;
+
+    // Emission base of bucket b: the sum of its starts over the tiles.
+    uint32_t below = 0;
+    for (uint32_t t = lane; t < nt; t += 64) below += tm0[t];
+    below = uniform(wave_sum(below));
+
+    uint32_t n = 0;        // occupied slots (uniform)
+    uint32_t special = 0;  // packets of the key equal to the empty marker (uniform)
+
+    // Link table of sweep `sw` of 2^logS; false if an insert gave up.
+    auto build = [&](uint32_t logS, uint32_t sw) -> bool {
+      n = 0;
+      special = 0;
+      bool gave_up = false;
+      for (uint32_t g0 = 0; g0 < nt; g0 += 64) {
+        const uint32_t t = g0 + lane;
+        u64 mb = 0;
+        uint32_t len = 0;
+        if (t < nt) {
+          const uint32_t a = tm0[t], c = tm0[t + nt];
+          mb = u64(t) * T + a;
+          len = c - a;
+        }
+        // walk the concatenation of the group's segments, 64 keys per chunk
+        const uint32_t incl = wave_inclusive_scan(len);
+        const uint32_t elems = uniform(readlane(incl, 63));
+        mb -= incl - len;                       // base minus exclusive prefix
+        for (uint32_t v0 = 0; v0 < elems; v0 += 64 * LINK_MAXU) {
+          u64 key[LINK_MAXU];
+          uint32_t h[LINK_MAXU], add[LINK_MAXU];
+          bool ok[LINK_MAXU];
+#pragma unroll
+          for (int u = 0; u < LINK_MAXU; ++u) {
+            const uint32_t v = v0 + uint32_t(u) * 64u + lane;
+            uint32_t j = 0;
+#pragma unroll
+            for (uint32_t st = 32; st > 0; st >>= 1)
+              if (lane_take(incl, j + st - 1) <= v) j += st;
+            const u64 pos = ((u64(lane_take(uint32_t(mb >> 32), j)) << 32) |
+                             lane_take(uint32_t(mb), j)) + v;
+            ok[u] = v < elems;
+            const u64 kk = keys[ok[u] ? pos : 0ull];   // position 0 exists; masked below
+            key[u] = ok[u] ? kk : 0ull;
+          }
+#pragma unroll
+          for (int u = 0; u < LINK_MAXU; ++u) {
+            const u64 hh = link_pos(key[u]);
+            h[u] = uint32_t(hh);
+            ok[u] = ok[u] && !(logS && next64(hh, W.logB, logS) != sw);
+            add[u] = 1;
+            const bool spc = ok[u] && key[u] == EMPTY64;
+            special += __popcll(__ballot(spc));
+            if (spc) ok[u] = false;
+            // combine the lanes holding the first valid lane's key
+            const u64 vm = __ballot(ok[u]);
+            if (vm) {
+              const int first = __ffsll(static_cast<unsigned long long>(vm)) - 1;
+              const u64 k0 = (u64(readlane(uint32_t(key[u] >> 32), first)) << 32) |
+                             readlane(uint32_t(key[u]), first);
+              const bool same = ok[u] && key[u] == k0;
+              const uint32_t nsame = __popcll(__ballot(same));
+              if (nsame > 1 && same) {
+                if (int(lane) == first) add[u] = nsame;
+                else ok[u] = false;
+              }
+            }
+          }
+          int slot[LINK_MAXU];
+          bool fresh[LINK_MAXU];
+          if (!cas_insert<LINK_MAXU>(tk, S - 1, key, h, ok, slot, fresh, NSGC_MAX_PROBES))
+            gave_up = true;
+#pragma unroll
+          for (int u = 0; u < LINK_MAXU; ++u)
+            if (slot[u] >= 0) lds_add(&tc[slot[u]], add[u]);
+#pragma unroll
+          for (int u = 0; u < LINK_MAXU; ++u) {
+            const u64 m = __ballot(fresh[u]);
+            if (fresh[u]) occ[n + rank_below(m)] = uint16_t(slot[u]);
+            n += __popcll(m);
+          }
+        }
+      }
+      wave_fence();
+      return !__ballot(gave_up);
+    };
+
+    auto reset = [&]() {
+      for (uint32_t i = lane; i < n; i += 64) {
+        const uint32_t s = occ[i];
+        tk[s] = EMPTY64;
+        tc[s] = 0;
+      }
+      n = 0;
+      wave_fence();
+    };
+
+    auto count = [&]() {
+      for (uint32_t i = lane; i < n; i += 64) {
+        const uint32_t s = occ[i];
+        const u64 key = tk[s];
+        const uint32_t parts = entry_parts(tc[s], 1);
+        lds_add(&histR[top32(uint32_t(key >> 32), W.logR)], parts);
+        lds_add(&histC[top32(uint32_t(key), W.logC)], parts);
+      }
+      if (lane == 0 && special) {
+        const uint32_t parts = entry_parts(special, 1);
+        lds_add(&histR[top32(EMPTY32, W.logR)], parts);
+        lds_add(&histC[top32(EMPTY32, W.logC)], parts);
+      }
+      wave_fence();
+    };
+
+    // counts -> starts, published for phase C (and the phase-C sizes)
+    auto publish = [&]() {
+      wave_exclusive_scan_lds(histR, R);
+      wave_exclusive_scan_lds(histC, C);
+      for (uint32_t i = lane; i <= R; i += 64) rec[B + u64(i) * B + b] = histR[i];
+      for (uint32_t i = lane; i <= C; i += 64) rec[B + u64(R + 1) * B + u64(i) * B + b] = histC[i];
+    };
+
+    // entries at the counted positions; empties the table
+    auto emit = [&]() {
+      NSGC_GLOBAL u64* er = gptr(P->emit_row) + W.ws + below;
+      NSGC_GLOBAL u64* ec = gptr(P->emit_col) + W.ws + below;
+      for (uint32_t i = lane; i < n; i += 64) {
+        const uint32_t s = occ[i];
+        const u64 key = tk[s];
+        const uint32_t cnt = tc[s];
+        tk[s] = EMPTY64;
+        tc[s] = 0;
+        const uint32_t parts = entry_parts(cnt, 1);
+        const uint32_t ar = lds_add(&histR[top32(uint32_t(key >> 32), W.logR)], parts);
+        const uint32_t ac = lds_add(&histC[top32(uint32_t(key), W.logC)], parts);
+        write_entry(er, ar, uint32_t(key >> 32), cnt, 1, parts);
+        write_entry(ec, ac, uint32_t(key), cnt, 1, parts);
+      }
+      if (lane == 0 && special) {
+        const uint32_t parts = entry_parts(special, 1);
+        write_entry(er, lds_add(&histR[top32(EMPTY32, W.logR)], parts), EMPTY32, special, 1, parts);
+        write_entry(ec, lds_add(&histC[top32(EMPTY32, W.logC)], parts), EMPTY32, special, 1, parts);
+      }
+      n = 0;
+      wave_fence();
+    };
+
+    uint32_t links = 0, sum = 0, mx = 0;
+    bool abandoned = false;
+    for (uint32_t logS = 0;; ++logS) {
+      if (logS > P->max_sweeps_log2) { abandoned = true; break; }
+      links = sum = mx = 0;
+      for (uint32_t i = lane; i <= R; i += 64) histR[i] = 0;
+      for (uint32_t i = lane; i <= C; i += 64) histC[i] = 0;
+      wave_fence();
+      bool failed = false;
+      const uint32_t passes = logS ? 2u : 1u;
+      for (uint32_t pass = 0; pass < passes && !failed; ++pass) {
+        if (pass == 1) publish();
+        for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
+          if (!build(logS, sw)) { failed = true; reset(); break; }
+          if (pass == 1) { emit(); continue; }
+          for (uint32_t i = lane; i < n; i += 64) {
+            const uint32_t c = tc[occ[i]];
+            sum += c;
+            mx = max(mx, c);
+          }
+          links += n + (special ? 1u : 0u);
+          if (lane == 0 && special) {
+            sum += special;
+            mx = max(mx, special);
+          }
+          count();
+          if (logS == 0) {
+            publish();
+            emit();
+          } else {
+            reset();
+          }
+        }
+      }
+      if (!failed) break;
+    }
+    if (abandoned) {   // empty row/column segments, so phase C reads nothing here
+      for (uint32_t i = lane; i <= R; i += 64) rec[B + u64(i) * B + b] = 0;
+      for (uint32_t i = lane; i <= C; i += 64) rec[B + u64(R + 1) * B + u64(i) * B + b] = 0;
+    }
+    if (lane == 0) rec[b] = below;
+    sum = wave_sum(sum);
+    mx = wave_max(mx);
+    if (lane == 0) {   // the bucket's totals, combined per window by k_finish
+      const v4u32 part = {sum, links, mx, abandoned ? 1u : 0u};
+      gptr(reinterpret_cast<v4u32*>(P->partB))[it] = part;
+    }
   }
 }
 
@@ -1054,9 +1441,33 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
   }
 
   const uint32_t items = P->itemsC;
+  const uint32_t wave = uniform(threadIdx.x >> 6), lane = lane_id();
+  // The first group of an item's segments (lane l of wave w: link bucket
+  // w + WAVES * l), loaded for the next item while the current one finishes.
+  auto load_first = [&](uint32_t it, SegPre& pre) {
+    const uint32_t wi = sload(P->itemwinC + it);
+    const nsgc_win_desc W = sload_words(P->win + wi);
+    const uint32_t k = it - sload(P->prefC + wi);
+    const uint32_t B = 1u << W.logB, R = 1u << W.logR;
+    const bool is_row = k < R;
+    const NSGC_GLOBAL uint32_t* rec = gptr(P->lbmeta) + W.lbmeta;
+    const NSGC_GLOBAL uint32_t* st0 =
+        rec + B + (is_row ? u64(k) * B : u64(R + 1) * B + u64(k - R) * B);
+    const uint32_t lb = wave + uint32_t(WAVES) * lane;
+    pre.base = 0;
+    pre.len = 0;
+    if (lb < B) {
+      const uint32_t s0 = st0[lb], s1 = st0[lb + B];
+      pre.base = u64(rec[lb]) + s0;
+      pre.len = s1 - s0;
+    }
+  };
+  SegPre next_pre = {0, 0};
+  bool have_next = false;
+
   ItemQueue q(gptr(&P->queue[2][0]), misc + 7, NSGC_QCLASSES,
               P->order_items ? gptr(P->order) : nullptr);
-  for (uint32_t item = q.first(items); item < items; item = q.read()) {
+  for (uint32_t item = q.first(items); item != NO_ITEM; item = q.read()) {
     const uint32_t it = uniform(item);
     const uint32_t wi = sload(P->itemwinC + it);
     const nsgc_win_desc W = sload_words(P->win + wi);
@@ -1070,6 +1481,15 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
         rec + B + (is_row ? u64(bucket) * B : u64(R + 1) * B + u64(bucket) * B);
     const NSGC_GLOBAL uint32_t* st1 = st0 + B;
     const NSGC_GLOBAL u64* em = gptr(is_row ? P->emit_row : P->emit_col) + W.ws;
+
+    SegPre pre;
+    if (have_next) pre = next_pre;
+    else load_first(it, pre);
+    have_next = false;
+    // thread 0 starts looking up the next item (its order entry) now and
+    // names it to the workgroup at the end of the gather
+    q.resolve(items);
+    bool fetched = false;
 
     auto seg = [&](uint32_t lb, u64& base, uint32_t& len) {
       const uint32_t s0 = st0[lb], s1 = st1[lb];
@@ -1126,7 +1546,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          h[u] = is_row ? row_hash(id[u]) : col_hash(id[u]);
+          h[u] = id[u];
           ok[u] = okin[u] && !(logS && next32(h[u], logK, logS) != sw);
           if (ok[u] && id[u] == EMPTY32) {
             lds_add(&misc[2], pk[u]);
@@ -1162,7 +1582,17 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
           }
         }
         (void)fresh;
+      }, &pre, [&]() {
+        if (threadIdx.x == 0 && !fetched) misc[6] = q.pending_item;
       });
+      if (!fetched) {   // the next item's first segments, loaded behind this item
+        fetched = true;
+        const uint32_t nx = uniform(misc[6]);
+        if (nx != NO_ITEM) {
+          load_first(nx, next_pre);
+          have_next = true;
+        }
+      }
     };
 
     bool abandoned = false;
@@ -1184,18 +1614,78 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
       }
       if (!failed) break;
     }
-    q.resolve(items);
     block_sum_max2_to0(n, mp, ml, st.red);   // thread 0 holds the bucket's totals
-    if (threadIdx.x == 0) {
-      NSGC_GLOBAL u64* o = gptr(P->out) + u64(W.out_index) * 9 + (is_row ? 3 : 6);
-      if (abandoned)
-        __hip_atomic_fetch_or(o - (is_row ? 3 : 6), NSGC_INVALID_BIT, __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_AGENT);
-      stat_add(o + 0, n);
-      stat_max(o + 1, mp);
-      stat_max(o + 2, ml);
+    if (threadIdx.x == 0) {   // combined per window by k_finish
+      const v4u32 part = {n, mp, ml, abandoned ? 1u : 0u};
+      gptr(reinterpret_cast<v4u32*>(P->partC))[it] = part;
     }
     q.stage_next(items);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-window statistics of the partitioned windows from the bucket totals of
+// phases B and C: stats 0-2 sum / sum / max over the link buckets, 3-5 and
+// 6-8 count / max / max over the row and the column buckets.  Buckets
+// partition the window's links and its sources (destinations), so the sums
+// are exact.  Plain stores of partial totals in the earlier phases keep
+// device-scope atomics off their per-item paths.  One workgroup per window.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_finish(nsgc_dev_plan* P) {
+  // per wavefront: link sum, link count, row count, column count; maxima of
+  // link packets, row packets, fan-out, column packets, fan-in; invalid flag
+  __shared__ uint32_t red[4][10];
+  const uint32_t tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
+  for (uint32_t wi = blockIdx.x; wi < P->num_part; wi += gridDim.x) {
+    const nsgc_win_desc W = gload(P->win + wi);
+    const uint32_t B = 1u << W.logB, R = 1u << W.logR, C = 1u << W.logC;
+    const NSGC_GLOBAL v4u32* pb = gptr(reinterpret_cast<const v4u32*>(P->partB)) + gptr(P->prefB)[wi];
+    const NSGC_GLOBAL v4u32* pc = gptr(reinterpret_cast<const v4u32*>(P->partC)) + gptr(P->prefC)[wi];
+    // every sum is at most the window's packet count, below 2^32
+    uint32_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t i = tid; i < B; i += 256) {
+      const v4u32 x = pb[i];
+      v[0] += x.x;
+      v[1] += x.y;
+      v[4] = max(v[4], x.z);
+      v[9] |= x.w;
+    }
+    for (uint32_t i = tid; i < R + C; i += 256) {
+      const v4u32 x = pc[i];
+      const bool row = i < R;
+      v[row ? 2 : 3] += x.x;
+      v[row ? 5 : 7] = max(v[row ? 5 : 7], x.y);
+      v[row ? 6 : 8] = max(v[row ? 6 : 8], x.z);
+      v[9] |= x.w;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+#pragma unroll
+    for (int k = 4; k < 10; ++k) v[k] = wave_max(v[k]);
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < 10; ++k) red[wv][k] = v[k];
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t t[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) {
+        t[k] = red[0][k];
+        for (int q = 1; q < 4; ++q) t[k] = k < 4 ? t[k] + red[q][k] : max(t[k], red[q][k]);
+      }
+      NSGC_GLOBAL u64* o = gptr(P->out) + u64(W.out_index) * 9;
+      o[0] = u64(t[0]) | (t[9] ? NSGC_INVALID_BIT : 0ull);
+      o[1] = t[1];
+      o[2] = t[4];
+      o[3] = t[2];
+      o[4] = t[5];
+      o[5] = t[6];
+      o[6] = t[3];
+      o[7] = t[7];
+      o[8] = t[8];
+    }
     __syncthreads();
   }
 }
@@ -1232,6 +1722,16 @@ hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_bu
   return hipGetLastError();
 }
 
+hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(k_links_wave, dim3(grid), dim3(WAVE_NT), lds, s, const_cast<nsgc_dev_plan*>(P));
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const nsgc_dev_plan* P, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(grid), dim3(256), 0, s, const_cast<nsgc_dev_plan*>(P));
+  return hipGetLastError();
+}
+
 hipError_t launch_order(const nsgc_dev_plan* P, hipStream_t s) {
   hipLaunchKernelGGL(k_order, dim3(1), dim3(NSGC_BLOCK), 0, s, const_cast<nsgc_dev_plan*>(P));
   return hipGetLastError();
@@ -1258,9 +1758,12 @@ hipError_t resident_blocks(int which, uint32_t tile_log2, size_t lds, int* block
     case 2: f = reinterpret_cast<const void*>(&k_links<false>); break;
     case 4: f = reinterpret_cast<const void*>(&k_links<true>); break;
     case 3: f = reinterpret_cast<const void*>(&k_rowcol); break;
+    case 5: f = reinterpret_cast<const void*>(&k_links_wave); break;
     default: return hipErrorInvalidValue;
   }
-  const int threads = which == 1 && tile_log2 == 14 ? NSGC_BLOCK * PART14_SCALE : NSGC_BLOCK;
+  const int threads = which == 1 && tile_log2 == 14 ? NSGC_BLOCK * PART14_SCALE
+                      : which == 5                  ? WAVE_NT
+                                                    : NSGC_BLOCK;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, threads, lds);
 }
 
@@ -1268,7 +1771,7 @@ hipError_t allow_large_lds(size_t bytes) {
   const int b = int(bytes);
   const void* fns[] = {
       reinterpret_cast<const void*>(&k_small),         reinterpret_cast<const void*>(&k_links<false>),
-      reinterpret_cast<const void*>(&k_links<true>),
+      reinterpret_cast<const void*>(&k_links<true>),   reinterpret_cast<const void*>(&k_links_wave),
       reinterpret_cast<const void*>(&k_rowcol),        reinterpret_cast<const void*>(&k_partition<4>),
       reinterpret_cast<const void*>(&k_partition<8>),  reinterpret_cast<const void*>(&k_partition<16>),
       reinterpret_cast<const void*>(&k_partition<32 / PART14_SCALE, NSGC_BLOCK * PART14_SCALE>)};

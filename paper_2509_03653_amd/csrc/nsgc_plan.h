@@ -9,15 +9,19 @@
 //   small : n <= small_max (including empty windows).  One workgroup computes
 //           the window entirely in LDS (link, row and column tables at once).
 //   part  : everything else, in three phases over the window's packets:
-//     A  partition: tiles of 2^tile_log2 packets; each tile is reordered by
-//        link bucket (top bits of a 64-bit mix of the packed (src,dst) key)
-//        and written to the window's key region, with per-tile bucket starts.
+//     A  partition: tiles of 2^tile_log2 packets; each packet becomes the
+//        hashed link key row_hash(src) << 32 | col_hash(dst) (a bijection of
+//        the pair), each tile is reordered by link bucket (top bits of the
+//        key's position mix) and written to the window's key region, with
+//        per-tile bucket starts.  All later phases work on these hashed
+//        identities, so they never hash again.
 //     B  link aggregation: one item per link bucket gathers its segments from
 //        every tile into an LDS hash table (key -> packet count).  This gives
 //        A's non-zeros: sum, count and max per bucket (stats 0-2).  The
 //        bucket's links are then combined per source and per destination
-//        and emitted as (src, packets, links) grouped by row bucket and
-//        (dst, packets, links) grouped by column bucket, into the bucket's own
+//        and emitted as (row_hash(src), packets, links) grouped by row
+//        bucket and (col_hash(dst), packets, links) grouped by column bucket
+//        (the top bits of the hashed id), into the bucket's own
 //        emission region (as many slots as it has packets).  A source with
 //        many links thus leaves one entry per link bucket, not one per link.
 //     C  row / column aggregation: one item per row bucket and per column
@@ -46,6 +50,10 @@
 #define NSGC_ORDER_MAX 16384
 #define NSGC_ENT_PACKET_BITS 19
 #define NSGC_ENT_LINK_BITS 13
+// Phase B one wavefront per link bucket (k_links_wave): LDS table slots per
+// wavefront, and the most row (or column) buckets such a window may have.
+#define NSGC_WAVE_SLOTS_LOG2 9
+#define NSGC_WAVE_MAX_RC 256
 
 struct nsgc_small_desc {        // 16 bytes
   int64_t in_begin;             // index of the window's first packet
@@ -62,7 +70,8 @@ struct nsgc_win_desc {          // 64 bytes
   uint32_t out_index;           // window index in out_stats
   uint32_t ntiles;              // partition tiles
   uint32_t counter;             // index of the window among partitioned windows
-  uint8_t logB, logR, logC, pad0;
+  uint8_t logB, logR, logC;
+  uint8_t wave;                 // 1: phase B runs one wavefront per link bucket
   uint32_t pad1[3];
 };
 
@@ -88,19 +97,25 @@ struct nsgc_dev_plan {          // header of the device plan buffer
   unsigned long long* emit_col; // column entries (dst, links, packets)
   uint32_t* tilemeta;
   uint32_t* lbmeta;
-  uint32_t* rcsize;             // [itemsC] entries per phase-C item (cleared by phase A,
-                                //   summed by phase B)
+  uint32_t* rcsize;             // [itemsC] size of each phase-C item (packets of its row or
+                                //   column bucket in the window's first tile, by phase A)
   uint32_t* order;              // [itemsC] phase-C items, large ones first
+  uint32_t* partB;              // [itemsB][4] link-bucket totals: packets, links, max, invalid
+  uint32_t* partC;              // [itemsC][4] row/column-bucket totals: ids, max packets,
+                                //   max links, invalid
   const nsgc_small_desc* small;
   const nsgc_win_desc* win;
   const uint32_t* prefA;        // [num_part + 1] first phase-A item of each window
   const uint32_t* prefB;        // [num_part + 1] first phase-B item
   const uint32_t* prefC;        // [num_part + 1] first phase-C item
   const uint32_t* itemwinB;     // [itemsB] window (index among partitioned) of each phase-B item
+  const uint32_t* mapBb;        // phase-B items of workgroup windows (null: items 0..itemsBb)
+  const uint32_t* mapBw;        // phase-B items of wavefront windows (null: items 0..itemsBw)
   const uint32_t* itemwinC;     // [itemsC] window of each phase-C item
   uint32_t num_small;
   uint32_t num_part;
   uint32_t itemsA, itemsB, itemsC;
+  uint32_t itemsBb, itemsBw;    // phase-B items of workgroup / wavefront windows
   uint32_t tile_log2;
   uint32_t link_slots_log2;
   uint32_t rc_slots_log2;
@@ -108,9 +123,9 @@ struct nsgc_dev_plan {          // header of the device plan buffer
   uint32_t max_sweeps_log2;     // overflow sweeps allowed before a bucket is abandoned
   uint32_t combine_probes;      // 0: per-link emission; else probe limit of the combining table
   uint32_t order_items;         // 1: phase C takes its items in the order of `order`
-  // Work-queue counters of the small, B and C kernels.  Uploaded as zero
-  // with every plan.
-  uint32_t queue[3][NSGC_QCLASSES * NSGC_QSTRIDE];
+  // Work-queue counters of the small, B (workgroup), C and B (wavefront)
+  // kernels.  Uploaded as zero with every plan.
+  uint32_t queue[4][NSGC_QCLASSES * NSGC_QSTRIDE];
 };
 
 #endif  // NSGC_PLAN_H_

@@ -33,6 +33,7 @@ void default_tune(nsgc_tune* t) {
     t->cls[k].link_target = 2048;
     t->cls[k].row_target = 4096;
     t->cls[k].col_target = 4096;
+    t->cls[k].wave_target = 256;
   }
 }
 
@@ -49,6 +50,7 @@ int check_tune(const nsgc_tune& t) {
   for (int k = 0; k <= 32; ++k) {
     const nsgc_tune_class& c = t.cls[k];
     if (c.link_target < 64 || c.row_target < 64 || c.col_target < 64) return NSGC_ERR_INVALID_ARG;
+    if (c.wave_target != 0 && (c.wave_target < 64 || c.wave_target > 2048)) return NSGC_ERR_INVALID_ARG;
   }
   return NSGC_OK;
 }
@@ -72,6 +74,9 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
   p->prefC.clear();
   p->itemwinB.clear();
   p->itemwinC.clear();
+  p->mapBb.clear();
+  p->mapBw.clear();
+  p->itemsBb = p->itemsBw = 0;
   p->tier.assign(size_t(num_windows), 0);
   p->ws_elems = p->tilemeta_words = p->lbmeta_words = 0;
   p->tile_log2 = uint32_t(tune.tile_log2);
@@ -107,6 +112,14 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
     d.logB = uint8_t(std::min(ceil_log2((n + uint64_t(tc.link_target) - 1) / uint64_t(tc.link_target)), capB));
     d.logR = uint8_t(std::min(ceil_log2((n + uint64_t(tc.row_target) - 1) / uint64_t(tc.row_target)), capRC));
     d.logC = uint8_t(std::min(ceil_log2((n + uint64_t(tc.col_target) - 1) / uint64_t(tc.col_target)), capRC));
+    // one wavefront per link bucket when the window's buckets fit its tables
+    if (tc.wave_target > 0 && (1u << d.logR) <= NSGC_WAVE_MAX_RC && (1u << d.logC) <= NSGC_WAVE_MAX_RC) {
+      const int lw = ceil_log2((n + uint64_t(tc.wave_target) - 1) / uint64_t(tc.wave_target));
+      if (lw <= capB) {
+        d.logB = uint8_t(lw);
+        d.wave = 1;
+      }
+    }
     d.ntiles = uint32_t((n + tile - 1) / tile);
     d.counter = uint32_t(p->win.size());
     d.ws = p->ws_elems;
@@ -121,6 +134,8 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
     p->prefC.push_back(uint32_t(c));
     const uint32_t wi = uint32_t(p->win.size());
     p->itemwinB.insert(p->itemwinB.end(), size_t(B), wi);
+    std::vector<uint32_t>& m = d.wave ? p->mapBw : p->mapBb;
+    for (uint64_t i = 0; i < B; ++i) m.push_back(uint32_t(b + i));
     p->itemwinC.insert(p->itemwinC.end(), size_t(R + C), wi);
     a += d.ntiles;
     b += B;
@@ -134,6 +149,11 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
   p->itemsA = uint32_t(a);
   p->itemsB = uint32_t(b);
   p->itemsC = uint32_t(c);
+  p->itemsBb = uint32_t(p->mapBb.size());
+  p->itemsBw = uint32_t(p->mapBw.size());
+  // a kernel that takes every phase-B item needs no map
+  if (p->itemsBb == p->itemsB) p->mapBb.clear();
+  if (p->itemsBw == p->itemsB) p->mapBw.clear();
   return NSGC_OK;
 }
 
@@ -148,15 +168,18 @@ WsLayout HostPlan::layout() const {
   L.lbmeta = o;    o = align_up(o + size_t(lbmeta_words) * 4, 256);
   L.rcsize = o;    o = align_up(o + size_t(itemsC) * 4, 256);
   L.order = o;     o = align_up(o + size_t(itemsC) * 4, 256);
+  L.partB = o;     o = align_up(o + size_t(itemsB) * 16, 256);
+  L.partC = o;     o = align_up(o + size_t(itemsC) * 16, 256);
   L.total = std::max<size_t>(o, 256);
   return L;
 }
 
 namespace {
 struct PlanOffsets {
-  size_t small, win, prefA, prefB, prefC, itemwinB, itemwinC, total;
+  size_t small, win, prefA, prefB, prefC, itemwinB, itemwinC, mapBb, mapBw, total;
 };
-PlanOffsets plan_offsets(size_t ns, size_t nm, size_t nb, size_t nc) {
+PlanOffsets plan_offsets(size_t ns, size_t nm, size_t nb, size_t nc, size_t nbb = 0,
+                         size_t nbw = 0) {
   PlanOffsets o;
   size_t x = align_up(sizeof(nsgc_dev_plan), 64);
   o.small = x; x = align_up(x + ns * sizeof(nsgc_small_desc), 64);
@@ -166,13 +189,16 @@ PlanOffsets plan_offsets(size_t ns, size_t nm, size_t nb, size_t nc) {
   o.prefC = x; x = align_up(x + (nm + 1) * 4, 64);
   o.itemwinB = x; x = align_up(x + nb * 4, 64);
   o.itemwinC = x; x = align_up(x + nc * 4, 64);
+  o.mapBb = x; x = align_up(x + nbb * 4, 64);
+  o.mapBw = x; x = align_up(x + nbw * 4, 64);
   o.total = x;
   return o;
 }
 }  // namespace
 
 size_t HostPlan::plan_bytes() const {
-  return plan_offsets(small.size(), win.size(), itemwinB.size(), itemwinC.size()).total;
+  return plan_offsets(small.size(), win.size(), itemwinB.size(), itemwinC.size(), mapBb.size(),
+                      mapBw.size()).total;
 }
 
 size_t plan_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune& t) {
@@ -191,12 +217,20 @@ size_t plan_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune& t) 
   const uint64_t capRC = uint64_t(1) << t.max_rc_buckets_log2;
   const uint64_t nb = std::min<uint64_t>(2 * P / lt + 2 * W, W * capB);
   const uint64_t nc = std::min<uint64_t>(4 * P / rt + 4 * W, 2 * W * capRC);
-  return plan_offsets(size_t(W), size_t(W), size_t(nb), size_t(nc)).total + 1024;
+  // the wavefront buckets (wave_target >= 64) may outnumber the workgroup ones
+  uint64_t wt = ~uint64_t(0);
+  for (int k = 0; k <= 32; ++k)
+    if (t.cls[k].wave_target > 0) wt = std::min<uint64_t>(wt, uint64_t(t.cls[k].wave_target));
+  const uint64_t nbw = wt == ~uint64_t(0) ? 0 : std::min<uint64_t>(2 * P / wt + 2 * W, W * capB);
+  const uint64_t nb_all = std::max(nb, nbw);
+  return plan_offsets(size_t(W), size_t(W), size_t(nb_all), size_t(nc), size_t(nb_all),
+                      size_t(nb_all)).total + 1024;
 }
 
 void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const uint32_t* src,
                          const uint32_t* dst, void* out) const {
-  const PlanOffsets o = plan_offsets(small.size(), win.size(), itemwinB.size(), itemwinC.size());
+  const PlanOffsets o = plan_offsets(small.size(), win.size(), itemwinB.size(), itemwinC.size(),
+                                     mapBb.size(), mapBw.size());
   const WsLayout L = layout();
   char* base = static_cast<char*>(buf);
   std::memset(base, 0, align_up(sizeof(nsgc_dev_plan), 64));
@@ -212,6 +246,8 @@ void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const ui
   h.lbmeta = reinterpret_cast<uint32_t*>(dev_ws + L.lbmeta);
   h.rcsize = reinterpret_cast<uint32_t*>(dev_ws + L.rcsize);
   h.order = reinterpret_cast<uint32_t*>(dev_ws + L.order);
+  h.partB = reinterpret_cast<uint32_t*>(dev_ws + L.partB);
+  h.partC = reinterpret_cast<uint32_t*>(dev_ws + L.partC);
   h.small = reinterpret_cast<const nsgc_small_desc*>(dev_plan + o.small);
   h.win = reinterpret_cast<const nsgc_win_desc*>(dev_plan + o.win);
   h.prefA = reinterpret_cast<const uint32_t*>(dev_plan + o.prefA);
@@ -219,6 +255,10 @@ void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const ui
   h.prefC = reinterpret_cast<const uint32_t*>(dev_plan + o.prefC);
   h.itemwinB = reinterpret_cast<const uint32_t*>(dev_plan + o.itemwinB);
   h.itemwinC = reinterpret_cast<const uint32_t*>(dev_plan + o.itemwinC);
+  h.mapBb = mapBb.empty() ? nullptr : reinterpret_cast<const uint32_t*>(dev_plan + o.mapBb);
+  h.mapBw = mapBw.empty() ? nullptr : reinterpret_cast<const uint32_t*>(dev_plan + o.mapBw);
+  h.itemsBb = itemsBb;
+  h.itemsBw = itemsBw;
   h.num_small = uint32_t(small.size());
   h.num_part = uint32_t(win.size());
   h.itemsA = itemsA;
@@ -239,6 +279,8 @@ void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const ui
   std::memcpy(base + o.prefC, prefC.data(), prefC.size() * 4);
   if (!itemwinB.empty()) std::memcpy(base + o.itemwinB, itemwinB.data(), itemwinB.size() * 4);
   if (!itemwinC.empty()) std::memcpy(base + o.itemwinC, itemwinC.data(), itemwinC.size() * 4);
+  if (!mapBb.empty()) std::memcpy(base + o.mapBb, mapBb.data(), mapBb.size() * 4);
+  if (!mapBw.empty()) std::memcpy(base + o.mapBw, mapBw.data(), mapBw.size() * 4);
 }
 
 }  // namespace nsgc

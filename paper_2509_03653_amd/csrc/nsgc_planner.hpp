@@ -15,7 +15,8 @@ namespace nsgc {
 
 // Workspace regions of one batch, as byte offsets from the workspace base.
 struct WsLayout {
-  size_t keys = 0, emit_row = 0, emit_col = 0, tilemeta = 0, lbmeta = 0, rcsize = 0, order = 0;
+  size_t keys = 0, emit_row = 0, emit_col = 0, tilemeta = 0, lbmeta = 0, rcsize = 0, order = 0,
+         partB = 0, partC = 0;
   size_t total = 0;
 };
 
@@ -24,6 +25,8 @@ struct HostPlan {
   std::vector<nsgc_win_desc> win;
   std::vector<uint32_t> prefA, prefB, prefC;
   std::vector<uint32_t> itemwinB, itemwinC;   // window of each phase-B / phase-C item
+  std::vector<uint32_t> mapBb, mapBw;         // phase-B items by kernel (empty: identity)
+  uint32_t itemsBb = 0, itemsBw = 0;
   int64_t ws_elems = 0;        // packets of the partitioned windows
   int64_t tilemeta_words = 0;  // u32 words of tile bucket starts
   int64_t lbmeta_words = 0;    // u32 words of link-bucket records

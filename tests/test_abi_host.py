@@ -125,6 +125,14 @@ def test_plan_tiers_and_cutover():
         cls = int(np.floor(np.log2(sizes[i])))
         lt = t.cls[cls].link_target
         want = min(int(np.ceil(np.log2(max(1, -(-sizes[i] // lt))))), t.max_link_buckets_log2)
+        # a wave target takes over when the window's row and column buckets
+        # fit the wavefront kernel and its bucket count stays within the cap
+        wt = t.cls[cls].wave_target
+        if (wt > 0 and (1 << int(p["log2_row_buckets"][i])) <= 256
+                and (1 << int(p["log2_col_buckets"][i])) <= 256):
+            lw = int(np.ceil(np.log2(max(1, -(-sizes[i] // wt)))))
+            if lw <= t.max_link_buckets_log2:
+                want = lw
         assert p["log2_link_buckets"][i] == want
     assert p["workspace_bytes"] >= 24 * (sum(sizes[3:]))
 

@@ -169,6 +169,13 @@ TUNES = {
     "combine_fallback": dict(combine_probes=1),
     "combine_fallback_tight": dict(combine_probes=2, link_slots_log2=10,
                                    cls=[[512, 4096, 4096]] * 33),
+    # phase B one wavefront per bucket: off, tiny buckets, and buckets far
+    # beyond the wavefront table (overflow sweeps inside a wavefront)
+    "workgroup_phase_b": dict(cls=[[2048, 4096, 4096, 0]] * 33),
+    "wave_tiny_buckets": dict(cls=[[2048, 4096, 4096, 64]] * 33, max_link_buckets_log2=12),
+    "wave_forced_sweeps": dict(cls=[[2048, 4096, 4096, 2048]] * 33),
+    "wave_many_rc_buckets": dict(cls=[[2048, 256, 256, 128]] * 33, max_link_buckets_log2=12,
+                                 max_rc_buckets_log2=12),
 }
 
 
@@ -184,6 +191,23 @@ def test_every_tuning_gives_identical_results(name):
     nsgc.set_tune(nsgc.Tune.from_dict(base))
     check(src, dst, wl.offsets, f"tune {name} zipf")
     check(s2, d2, off, f"tune {name} mixed sizes", forms=("batched", "plain"))
+
+
+def test_wavefront_and_workgroup_windows_in_one_batch():
+    # windows up to 2^18 packets take link aggregation one wavefront per bucket,
+    # larger ones one workgroup per bucket; both kernels draw their items from
+    # their own list of the batch's phase-B items
+    sizes = [5000, 300000, 70000, 1 << 19, 1500, 0, 2000, 262144, 262145, 40000]
+    off = synth.offsets_from_sizes(sizes)
+    wl = synth.zipf_batch(seed=3, num_windows=1, log2_window=4)
+    src, dst = synth.fill(off, 12, wl.src_dist, wl.dst_dist)
+    p = nsgc.plan_inspect(off)
+    t = nsgc.get_tune()
+    wave = [sizes[i] > t.small_max and int(p["log2_link_buckets"][i]) > int(
+        np.ceil(np.log2(-(-sizes[i] // t.cls[int(np.log2(sizes[i]))].link_target))))
+        for i in range(len(sizes)) if sizes[i] > 0]
+    assert any(wave) and not all(wave)
+    check(src, dst, off, "wavefront and workgroup windows", forms=("batched", "plain", "graph"))
 
 
 def test_repeated_runs_identical_and_nonzero_first_offset():
