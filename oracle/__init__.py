@@ -64,6 +64,15 @@ def _load():
         lib.nsgc_oracle_unique_ips.argtypes = [
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
             ctypes.c_void_p, ctypes.c_int]
+        lib.nsgc_oracle_permute.restype = ctypes.c_uint64
+        lib.nsgc_oracle_permute.argtypes = [ctypes.c_uint64] * 3
+        lib.nsgc_oracle_unique_addresses.restype = ctypes.c_int64
+        lib.nsgc_oracle_unique_addresses.argtypes = [ctypes.c_void_p, ctypes.c_void_p,
+                                                     ctypes.c_int64, ctypes.c_void_p]
+        lib.nsgc_oracle_anonymize.restype = ctypes.c_int
+        lib.nsgc_oracle_anonymize.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                              ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p]
         lib.nsgc_oracle_window_entities.restype = ctypes.c_int
         lib.nsgc_oracle_window_entities.argtypes = [
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64] + [
@@ -116,6 +125,40 @@ def unique_ips(src, dst, offsets, threads: int = 1) -> np.ndarray:
         raise ValueError("oracle rejected its arguments (offsets must be >= 0 and "
                          "non-decreasing)")
     return out
+
+
+def permute(i: int, n: int, seed: int) -> int:
+    """pi(i) of the anonymization's seeded permutation of [0, n)."""
+    return int(_load().nsgc_oracle_permute(int(i), int(n), int(seed) & (2 ** 64 - 1)))
+
+
+def unique_addresses(src, dst) -> np.ndarray:
+    """The unique addresses of both columns in ascending order."""
+    src = np.ascontiguousarray(src, dtype=np.uint32)
+    dst = np.ascontiguousarray(dst, dtype=np.uint32)
+    out = np.zeros(max(2 * src.size, 1), dtype=np.uint32)
+    k = _load().nsgc_oracle_unique_addresses(src.ctypes.data, dst.ctypes.data, src.size,
+                                             out.ctypes.data)
+    return out[:k]
+
+
+def anonymize(src, dst, seed: int):
+    """Anonymized columns (Section IV, "IP Address Anonymization"): each address
+    becomes pi(its rank among the unique addresses in ascending order).
+    Returns (anon_src, anon_dst, N)."""
+    src = np.ascontiguousarray(src, dtype=np.uint32)
+    dst = np.ascontiguousarray(dst, dtype=np.uint32)
+    if src.size != dst.size:
+        raise ValueError("src and dst differ in length")
+    a = np.zeros(src.size, np.uint32)
+    b = np.zeros(src.size, np.uint32)
+    n = np.zeros(1, np.uint64)
+    rc = _load().nsgc_oracle_anonymize(src.ctypes.data, dst.ctypes.data, src.size,
+                                       int(seed) & (2 ** 64 - 1), a.ctypes.data, b.ctypes.data,
+                                       n.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return a, b, int(n[0])
 
 
 def window_entities(src, dst, begin: int = 0, end: int | None = None) -> dict:

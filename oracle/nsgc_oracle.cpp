@@ -104,9 +104,93 @@ uint64_t unique_ips(const uint32_t* src, const uint32_t* dst, int64_t begin, int
   return static_cast<uint64_t>(ips.size());
 }
 
+// ---- anonymization (Section IV, "IP Address Anonymization") ----------------
+// The paper lists the unique addresses of the source and destination columns,
+// draws a random permutation of 0..N-1 by shuffling that sequence, and maps
+// the i-th unique address to the i-th value of the permutation.  Here the
+// unique addresses are listed in ascending order (what a sort-based unique
+// returns) and the shuffle is a seeded pseudo-random permutation, so that
+// the mapping is reproducible:
+//   b = the smallest even bit count with 2^b >= max(N, 4), h = b / 2;
+//   E(x) on [0, 2^b): split x into halves L = x >> h, R = x mod 2^h and run
+//     four Feistel rounds (L, R) <- (R, L xor F_r(R)), r = 0..3, with
+//     F_r(R) = mix(seed xor (r + 1) * 0x9E3779B97F4A7C15 xor R) mod 2^h,
+//     where mix is the SplitMix64 output function; E(x) = L * 2^h + R;
+//   pi(i) = the first of E(i), E(E(i)), ... that is below N (cycle walking,
+//     Black and Rogaway, "Ciphers with arbitrary finite domains", 2002).
+// A Feistel network is a bijection for any round function, and cycle walking
+// restricts a bijection of [0, 2^b) to one of [0, N).
+
+uint64_t splitmix_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t feistel(uint64_t x, int h, uint64_t seed) {
+  const uint64_t mask = (uint64_t(1) << h) - 1;
+  uint64_t L = x >> h, R = x & mask;
+  for (uint64_t r = 0; r < 4; ++r) {
+    const uint64_t f = splitmix_mix(seed ^ ((r + 1) * 0x9E3779B97F4A7C15ull) ^ R) & mask;
+    const uint64_t t = L ^ f;
+    L = R;
+    R = t;
+  }
+  return (L << h) | R;
+}
+
+uint64_t permute(uint64_t i, uint64_t N, uint64_t seed) {
+  if (N <= 1) return i;
+  int b = 2;
+  while ((uint64_t(1) << b) < N) b += 2;
+  uint64_t y = feistel(i, b / 2, seed);
+  while (y >= N) y = feistel(y, b / 2, seed);
+  return y;
+}
+
 }  // namespace
 
 extern "C" {
+
+// pi(i) of the anonymization's permutation of [0, N) for `seed` (see above).
+uint64_t nsgc_oracle_permute(uint64_t i, uint64_t N, uint64_t seed) { return permute(i, N, seed); }
+
+// The unique addresses of src[0..n) and dst[0..n) in ascending order; returns
+// their number N (out must hold 2n values).
+int64_t nsgc_oracle_unique_addresses(const uint32_t* src, const uint32_t* dst, int64_t n,
+                                     uint32_t* out) {
+  std::set<uint32_t> ips;
+  for (int64_t i = 0; i < n; ++i) {
+    ips.insert(src[i]);
+    ips.insert(dst[i]);
+  }
+  int64_t k = 0;
+  for (uint32_t v : ips) out[k++] = v;
+  return k;
+}
+
+// Anonymization of n packets: every address x of either column becomes
+// pi(rank of x among the unique addresses in ascending order).  Writes the
+// two anonymized columns and N; returns 0, or -1 for bad arguments.
+int nsgc_oracle_anonymize(const uint32_t* src, const uint32_t* dst, int64_t n, uint64_t seed,
+                          uint32_t* asrc, uint32_t* adst, uint64_t* num_ips) {
+  if (n < 0 || (n > 0 && (!src || !dst || !asrc || !adst)) || !num_ips) return -1;
+  std::set<uint32_t> ips;
+  for (int64_t i = 0; i < n; ++i) {
+    ips.insert(src[i]);
+    ips.insert(dst[i]);
+  }
+  const uint64_t N = ips.size();
+  std::map<uint32_t, uint64_t> id;
+  uint64_t rank = 0;
+  for (uint32_t v : ips) id[v] = permute(rank++, N, seed);
+  for (int64_t i = 0; i < n; ++i) {
+    asrc[i] = static_cast<uint32_t>(id[src[i]]);
+    adst[i] = static_cast<uint32_t>(id[dst[i]]);
+  }
+  *num_ips = N;
+  return 0;
+}
 
 // Nine statistics per window for windows [offsets[w], offsets[w+1]).
 // src, dst, offsets and out are host pointers; out holds 9*num_windows
