@@ -45,6 +45,11 @@ CALIB_BYTES = 1 << 30                     # calibration copy: 1 GiB read + 1 GiB
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_zipf_64x2^17.json")
 KERNEL_NAMES = {"small": "k_small", "partition": "k_partition", "links": "k_links",
                 "rowcol": "k_rowcol"}
+# the launches each timed phase covers (the link phase is one of two kernels,
+# the row/column phase includes the ordering and the per-window combine)
+PHASE_KERNELS = {"small": ["k_small"], "partition": ["k_partition"],
+                 "links": ["k_links_wave", "k_links"],
+                 "rowcol": ["k_order", "k_rowcol", "k_finish"]}
 
 
 def kernel_source_hash() -> str:
@@ -119,6 +124,112 @@ def time_loop(fn, steps, warmup, stream):
     return start.elapsed_time(end) / steps
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return "unknown"
+
+
+def oracle_single_thread(src, dst, offsets, budget_s: float):
+    """The oracle on one core over the whole batch (repeated within the
+    budget): packets/s."""
+    import oracle
+    n_all = int(offsets[-1] - offsets[0])
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.window_stats(src, dst, offsets, threads=1)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 20:
+            break
+    return n_all * reps / el
+
+
+def latency_leg(nsgc, torch, seed, calls=200):
+    """One window of 2^17 packets uniform over 4096 addresses: microseconds
+    per call of the graph form and of the direct batched form, each a loop
+    of back-to-back calls on one stream (launch-bound)."""
+    import synth
+    wl = synth.uniform_single(seed=seed)
+    src, dst = wl.generate()
+    off = wl.offsets
+    s = torch.from_numpy(src.view(np.int32)).cuda()
+    d = torch.from_numpy(dst.view(np.int32)).cuda()
+    out = torch.empty((1, 9), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    g = nsgc.Graph(wl.num_packets, 1)
+    try:
+        g.launch(s, d, off, out=out, stream=stream)
+        torch.cuda.synchronize()
+        import oracle
+        if not np.array_equal(out.cpu().numpy().view(np.uint64), oracle.window_stats(src, dst, off)):
+            raise SystemExit("parity check failed on the single uniform window")
+        ms_g = time_loop(lambda i: g.launch(s, d, off, out=out, stream=stream), calls, 20, stream)
+        ms_d = time_loop(lambda i: nsgc.window_stats(s, d, off, out=out, stream=stream), calls, 20,
+                         stream)
+    finally:
+        g.close()
+    st1 = oracle_single_thread(src, dst, off, 2.0)
+    return {"workload": WORKLOAD_TEXT["uniform_single"], "packets": wl.num_packets,
+            "graph_us_per_call": ms_g * 1e3, "direct_us_per_call": ms_d * 1e3,
+            "graph_packets_per_s": wl.num_packets / (ms_g * 1e-3),
+            "direct_packets_per_s": wl.num_packets / (ms_d * 1e-3),
+            "oracle_single_thread_packets_per_s": st1}
+
+
+def large_leg(nsgc, torch, seed, steps=5):
+    """128 windows of 2^23 skewed packets (2^30 in total): batched graph and
+    plain per-window forms, per-phase times and the dominant kernel's
+    roofline; parity-gated on four windows first."""
+    import synth
+    wl = synth.skewed_large(seed=seed)
+    src, dst = wl.generate()
+    off = wl.offsets
+    P, W = wl.num_packets, wl.num_windows
+    s = torch.from_numpy(src.view(np.int32)).cuda()
+    d = torch.from_numpy(dst.view(np.int32)).cuda()
+    out = torch.empty((W, 9), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    g = nsgc.Graph(P, W)
+    try:
+        g.launch(s, d, off, out=out, stream=stream)
+        torch.cuda.synchronize()
+        sample = sample_windows(W)
+        want = oracle_on(src, dst, off, sample, threads=len(sample))
+        if not np.array_equal(out.cpu().numpy().view(np.uint64)[sample], want):
+            raise SystemExit("parity check failed on the skewed 2^30-packet batch")
+        ms_g = time_loop(lambda i: g.launch(s, d, off, out=out, stream=stream), steps, 2, stream)
+    finally:
+        g.close()
+    ms_p = time_loop(lambda i: nsgc.window_stats_plain(s, d, off, out=out, stream=stream),
+                     max(steps // 2, 2), 1, stream)
+    phases = {k: [] for k in nsgc.PHASES}
+    for _ in range(steps):
+        _, ph = nsgc.window_stats_timed(s, d, off, out=out, stream=stream)
+        for k, v in ph.items():
+            phases[k].append(v)
+    phase_ms = {k: float(np.mean(v)) for k, v in phases.items()}
+    dom = max(phase_ms, key=phase_ms.get)
+    alg = algorithmic_bytes(P, W)
+    ach = alg / (phase_ms[dom] * 1e-3) / 1e9
+    del s, d
+    torch.cuda.empty_cache()
+    nsgc.release()
+    return {"workload": WORKLOAD_TEXT["skewed_large"], "windows": W, "packets": P,
+            "batched_ms_per_step": ms_g, "batched_packets_per_s": P / (ms_g * 1e-3),
+            "plain_ms_per_step": ms_p, "plain_packets_per_s": P / (ms_p * 1e-3),
+            "batched_over_plain": ms_p / ms_g, "phase_ms": phase_ms,
+            "step_roofline_frac": alg / (ms_g * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "roofline": {"bound": "hbm", "phase": dom, "kernels": PHASE_KERNELS[dom],
+                         "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS}}
+
+
 def cpu_baseline(src, dst, offsets, budget_s: float):
     """The oracle on the host cores: the whole batch, repeated while within
     budget; for batches too large for the budget, consecutive groups of
@@ -157,6 +268,13 @@ def cpu_baseline(src, dst, offsets, budget_s: float):
     return {"value": done_p / el, "unit": "packets/s", "cores": threads, "kind": "oracle",
             "sample": f"the first {done_w} of {W} windows ({done_p} packets, {el:.1f} s wall) "
                       f"with one window per thread"}
+
+
+def cpu_baseline_full(src, dst, offsets, budget_s: float):
+    r = cpu_baseline(src, dst, offsets, budget_s)
+    r["cpu_model"] = cpu_model()
+    r["single_thread_value"] = oracle_single_thread(src, dst, offsets, min(budget_s, 6.0))
+    return r
 
 
 def summarize_pmc(fetch_dir, write_dir):
@@ -288,6 +406,8 @@ def main():
     ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--serving-pool", type=int, default=256)
     ap.add_argument("--profile-steps", type=int, default=0)
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="skip the single-window latency and the 2^30-packet legs")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
 
@@ -381,7 +501,15 @@ def main():
 
     cpu = None
     if args.cpu_budget > 0:
-        cpu = cpu_baseline(src, dst, off, args.cpu_budget)
+        cpu = cpu_baseline_full(src, dst, off, args.cpu_budget)
+
+    extra = {}
+    if not args.no_extra_legs and args.workload == "zipf_batch":
+        extra["single_window"] = latency_leg(nsgc, torch, args.seed)
+        del ss, dd
+        torch.cuda.empty_cache()
+        nsgc.release()
+        extra["skewed_2e30"] = large_leg(nsgc, torch, args.seed)
 
     value = P / (ms_graph * 1e-3)
     line = {
@@ -407,12 +535,13 @@ def main():
         "step_algorithmic_GBs": alg / (ms_graph * 1e-3) / 1e9,
         "step_roofline_frac": alg / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "phase_ms": phase_ms,
-        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dominant], "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic},
+        "roofline": {"bound": "hbm", "phase": dominant, "kernels": PHASE_KERNELS[dominant],
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "cpu_baseline": cpu,
         "serving": serving,
     }
+    line.update(extra)
     if tuned is not None:
         line["autotune"] = {"tune": tuned["tune"], "default_ms": tuned.get("default_ms"),
                             "tuned_ms": tuned.get("ms"), "cached": tuned.get("cached")}

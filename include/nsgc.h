@@ -117,11 +117,12 @@ int nsgc_get_plain_mode(void);
 
 /*
  * Measurement form: the batched form with HIP events recorded on `stream`
- * around each kernel launch.  Waits for the work to finish and writes the
- * elapsed milliseconds of the four launches to phase_ms[0..3]: small-window
- * kernel, partition, link aggregation, row/column aggregation (0 for a phase
- * with no work).  Same arguments and results as nsgc_window_stats otherwise;
- * phase_ms is a host array of 4 floats.  Not usable under stream capture.
+ * around each phase.  Waits for the work to finish and writes the elapsed
+ * milliseconds of five phases to phase_ms[0..4]: small-window kernel,
+ * partition, link aggregation, row/column aggregation (with the per-window
+ * combine), and the large-window tier (0 for a phase with no work).  Same
+ * arguments and results as nsgc_window_stats otherwise; phase_ms is a host
+ * array of 5 floats.  Not usable under stream capture.
  */
 int nsgc_window_stats_timed(const uint32_t* src, const uint32_t* dst,
                             const int64_t* window_offsets, int64_t num_windows,
@@ -217,6 +218,10 @@ typedef struct nsgc_tune {
                                large share of the links), with this probe
                                limit before falling back to per-link entries */
   nsgc_tune_class cls[33];
+  int32_t large_min_log2;   /* windows of at least 2^k packets are computed by
+                               sorting instead of hash partitioning, one window
+                               at a time (20..33; 33 turns the tier off; the
+                               graph form and the entity outputs never use it) */
 } nsgc_tune;
 
 /* Current tuning of the calling process (defaults until set). */
@@ -267,6 +272,79 @@ int nsgc_graph_launch(nsgc_graph* g, const uint32_t* src, const uint32_t* dst,
                       const int64_t* window_offsets, int64_t num_windows,
                       nsgc_stats* out_stats, void* stream);
 int nsgc_graph_destroy(nsgc_graph* g);
+
+/*
+ * Per-entity outputs (Table III rows 3, 6 and 8 as vectors, and their
+ * reverses; Section IV "Graph Analytics" paragraph for the globally unique
+ * IP addresses).  For each window they list the non-zero entries of its
+ * traffic matrix A, its sources with r(s) and f(s), its destinations with
+ * c(d) and g(d), and count |{sources} U {destinations}|.  Addresses are the
+ * caller's (not hashed).  Use in two steps: nsgc_window_entity_counts gives
+ * each window's list lengths, the caller allocates the lists, and
+ * nsgc_window_entities fills them.
+ */
+typedef struct nsgc_entity_counts {   /* 32 bytes per window */
+  int64_t links;          /* nnz(A), = unique_links of nsgc_stats */
+  int64_t sources;        /* #{s : r(s) > 0}, = unique_sources */
+  int64_t destinations;   /* #{d : c(d) > 0}, = unique_destinations */
+  int64_t unique_ips;     /* |{s : r(s) > 0} U {d : c(d) > 0}| */
+} nsgc_entity_counts;
+
+/*
+ * The four counts per window.  Same src / dst / window_offsets / stream rules
+ * as nsgc_window_stats; counts is a DEVICE array of num_windows entries,
+ * fully overwritten.  Asynchronous.  Not usable under stream capture.
+ */
+int nsgc_window_entity_counts(const uint32_t* src, const uint32_t* dst,
+                              const int64_t* window_offsets, int64_t num_windows,
+                              nsgc_entity_counts* counts, void* stream);
+
+/*
+ * The lists.  links is a DEVICE array of rows of three int64 (src, dst,
+ * packets = A(src, dst)); sources holds rows (s, r(s), f(s)) and
+ * destinations rows (d, c(d), g(d)).  Window w writes rows
+ * [link_offsets[w], link_offsets[w+1]) of links, and likewise for the other
+ * two lists; the *_offsets are HOST arrays of num_windows + 1 non-decreasing
+ * values >= 0 (a window's range should hold at least its count).  Rows of a
+ * window come in no particular order.  counts (DEVICE, num_windows entries)
+ * receives the same counts as nsgc_window_entity_counts; where a window's
+ * range is shorter than its count, only that many of its rows are written
+ * (which ones is unspecified) and its count still reports the full number,
+ * so the caller can tell.  A list pointer may be NULL if its offsets give
+ * every window an empty range.  Asynchronous.  Not usable under stream
+ * capture.
+ */
+int nsgc_window_entities(const uint32_t* src, const uint32_t* dst,
+                         const int64_t* window_offsets, int64_t num_windows,
+                         const int64_t* link_offsets, int64_t* links,
+                         const int64_t* source_offsets, int64_t* sources,
+                         const int64_t* destination_offsets, int64_t* destinations,
+                         nsgc_entity_counts* counts, void* stream);
+
+/*
+ * Address anonymization (Section IV, "IP Address Anonymization"): every
+ * address of src[0..n) and dst[0..n) is replaced by a distinct integer in
+ * [0, N), N the number of unique addresses of the two columns.  The paper
+ * numbers the unique addresses and shuffles the numbers 0..N-1; here the
+ * unique addresses are numbered in ascending order of their value and the
+ * i-th maps to pi(i), pi a seeded pseudo-random permutation of [0, N): a
+ * four-round Feistel network on the smallest even bit count b with
+ * 2^b >= max(N, 4), round function F_r(R) = low b/2 bits of
+ * mix(seed ^ (r + 1) * 0x9E3779B97F4A7C15 ^ R) for r = 0..3 (mix: the
+ * SplitMix64 output function), restricted to [0, N) by cycle walking.  Equal
+ * addresses get equal values in both columns, so every window's statistics
+ * are unchanged.
+ *
+ * src, dst: DEVICE arrays of num_packets uint32 (num_packets < 2^31);
+ * anon_src, anon_dst: DEVICE outputs of num_packets uint32 (they may be src
+ * and dst themselves); num_addresses: DEVICE pointer to one uint64 that
+ * receives N.  Asynchronous on `stream`; argument errors are reported
+ * synchronously with nothing enqueued.  The workspace (about 48 bytes per
+ * packet) comes from the stream's pool, as for nsgc_window_stats.  Not
+ * usable under stream capture.
+ */
+int nsgc_anonymize(const uint32_t* src, const uint32_t* dst, int64_t num_packets, uint64_t seed,
+                   uint32_t* anon_src, uint32_t* anon_dst, uint64_t* num_addresses, void* stream);
 
 #ifdef __cplusplus
 }

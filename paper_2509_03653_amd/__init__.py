@@ -66,6 +66,9 @@ EXPORTS = (
     "nsgc_graph_create",
     "nsgc_graph_launch",
     "nsgc_graph_destroy",
+    "nsgc_window_entity_counts",
+    "nsgc_window_entities",
+    "nsgc_anonymize",
 )
 
 
@@ -100,11 +103,12 @@ class Tune(ctypes.Structure):
         ("max_sweeps_log2", ctypes.c_int32),
         ("combine_probes", ctypes.c_int32),
         ("cls", TuneClass * 33),
+        ("large_min_log2", ctypes.c_int32),
     ]
 
     SCALARS = ("small_max", "tile_log2", "link_slots_log2", "rc_slots_log2",
                "blocks_per_cu", "max_link_buckets_log2", "max_rc_buckets_log2",
-               "max_sweeps_log2", "combine_probes")
+               "max_sweeps_log2", "combine_probes", "large_min_log2")
 
     def to_dict(self) -> dict:
         d = {k: int(getattr(self, k)) for k in self.SCALARS}
@@ -177,6 +181,12 @@ def _lib():
         lib.nsgc_graph_launch.restype = i32
         lib.nsgc_graph_destroy.argtypes = [vp]
         lib.nsgc_graph_destroy.restype = i32
+        lib.nsgc_window_entity_counts.argtypes = [vp, vp, vp, i64, vp, vp]
+        lib.nsgc_window_entity_counts.restype = i32
+        lib.nsgc_window_entities.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.nsgc_window_entities.restype = i32
+        lib.nsgc_anonymize.argtypes = [vp, vp, i64, ctypes.c_uint64, vp, vp, vp, vp]
+        lib.nsgc_anonymize.restype = i32
         _LIB = lib
     return _LIB
 
@@ -278,13 +288,13 @@ NOALLOC_SCRATCH_BYTES = 128 << 20
 NOALLOC_PLAN_BYTES = 2 << 20
 
 
-PHASES = ("small", "partition", "links", "rowcol")
+PHASES = ("small", "partition", "links", "rowcol", "large")
 
 
 def window_stats_timed(src, dst, offsets, out=None, stream=None):
     """Measurement form (``nsgc_window_stats_timed``): returns ``(out, phase_ms)``
-    with the HIP-event duration of each of the four kernel launches."""
-    ms = (ctypes.c_float * 4)()
+    with the HIP-event duration of each phase (PHASES)."""
+    ms = (ctypes.c_float * len(PHASES))()
     fn = lambda *a: _lib().nsgc_window_stats_timed(*a, ms)  # noqa: E731
     out = _run(fn, "nsgc_window_stats_timed", src, dst, offsets, out, stream)
     return out, dict(zip(PHASES, (float(x) for x in ms)))
@@ -361,6 +371,96 @@ def plan_sizes(offsets) -> dict:
     _check(rc, "nsgc_plan_sizes")
     return {"plan_bytes": int(v[0]), "workspace_bytes": int(v[1]), "plan_bound": int(v[2]),
             "workspace_bound": int(v[3])}
+
+
+ENTITY_COUNT_NAMES = ("links", "sources", "destinations", "unique_ips")
+
+
+def window_entity_counts(src, dst, offsets, out=None, stream=None):
+    """Per-window list lengths of the entity outputs and the number of
+    globally unique IP addresses (``nsgc_window_entity_counts``): a (W, 4)
+    int64 tensor of links, sources, destinations and unique IPs."""
+    import torch
+    src = _device_u32(src, "src")
+    dst = _device_u32(dst, "dst")
+    off = _offsets(offsets)
+    w = len(off) - 1
+    if w > 0 and (off[-1] > src.numel() or off[-1] > dst.numel()):
+        raise ValueError("offsets run past the packet arrays")
+    if out is None:
+        out = torch.empty((max(w, 0), 4), dtype=torch.int64, device=src.device)
+    elif out.shape != (w, 4) or out.dtype != torch.int64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous (W, 4) int64 tensor")
+    with torch.cuda.device(src.device):
+        rc = _lib().nsgc_window_entity_counts(
+            ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+            ctypes.c_void_p(off.ctypes.data), w, ctypes.c_void_p(out.data_ptr()),
+            _stream_handle(stream, src.device))
+    _check(rc, "nsgc_window_entity_counts")
+    return out
+
+
+def window_entities(src, dst, offsets, stream=None):
+    """The entity lists of every window (``nsgc_window_entities``), sized by
+    a first ``nsgc_window_entity_counts`` call (which synchronises).  Returns a
+    dict: ``links`` (L, 3) rows (src, dst, packets), ``sources`` (S, 3) rows
+    (s, r(s), f(s)), ``destinations`` (D, 3) rows (d, c(d), g(d)), the
+    per-window row offsets of each list (``*_offsets``, numpy int64, W + 1),
+    and ``counts`` (W, 4).  Addresses are int64 values of the uint32 addresses;
+    rows within a window come in no particular order."""
+    import torch
+    src = _device_u32(src, "src")
+    dst = _device_u32(dst, "dst")
+    off = _offsets(offsets)
+    w = len(off) - 1
+    counts = window_entity_counts(src, dst, off, stream=stream)
+    if stream is None:
+        torch.cuda.current_stream(src.device).synchronize()
+    else:
+        stream.synchronize()
+    c = counts.cpu().numpy()
+    offs = [np.concatenate([[0], np.cumsum(c[:, k])]).astype(np.int64) for k in range(3)]
+    lists = [torch.empty((max(int(o[-1]), 0), 3), dtype=torch.int64, device=src.device)
+             for o in offs]
+    counts2 = torch.empty_like(counts)
+    with torch.cuda.device(src.device):
+        rc = _lib().nsgc_window_entities(
+            ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+            ctypes.c_void_p(off.ctypes.data), w,
+            ctypes.c_void_p(offs[0].ctypes.data), ctypes.c_void_p(lists[0].data_ptr()),
+            ctypes.c_void_p(offs[1].ctypes.data), ctypes.c_void_p(lists[1].data_ptr()),
+            ctypes.c_void_p(offs[2].ctypes.data), ctypes.c_void_p(lists[2].data_ptr()),
+            ctypes.c_void_p(counts2.data_ptr()), _stream_handle(stream, src.device))
+    _check(rc, "nsgc_window_entities")
+    return {"links": lists[0], "sources": lists[1], "destinations": lists[2],
+            "link_offsets": offs[0], "source_offsets": offs[1], "destination_offsets": offs[2],
+            "counts": counts2}
+
+
+def anonymize(src, dst, seed: int, out_src=None, out_dst=None, stream=None):
+    """Anonymized address columns (``nsgc_anonymize``): every address becomes
+    pi(its rank among the unique addresses of both columns in ascending
+    order), pi the seeded permutation of [0, N) described in include/nsgc.h.
+    Returns ``(anon_src, anon_dst, num_addresses)`` with the counts in a
+    one-element int64 tensor (all on the packets' device)."""
+    import torch
+    src = _device_u32(src, "src")
+    dst = _device_u32(dst, "dst")
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst differ in length")
+    out_src = torch.empty_like(src) if out_src is None else _device_u32(out_src, "out_src")
+    out_dst = torch.empty_like(dst) if out_dst is None else _device_u32(out_dst, "out_dst")
+    if out_src.numel() != src.numel() or out_dst.numel() != dst.numel():
+        raise ValueError("outputs must match the inputs' length")
+    num = torch.empty(1, dtype=torch.int64, device=src.device)
+    with torch.cuda.device(src.device):
+        rc = _lib().nsgc_anonymize(
+            ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.numel(),
+            ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), ctypes.c_void_p(out_src.data_ptr()),
+            ctypes.c_void_p(out_dst.data_ptr()), ctypes.c_void_p(num.data_ptr()),
+            _stream_handle(stream, src.device))
+    _check(rc, "nsgc_anonymize")
+    return out_src, out_dst, num
 
 
 class Graph:

@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libnsgc.so")
 
-SOURCES = ["nsgc_kernels.hip", "nsgc_noalloc.hip", "nsgc_api.cpp", "nsgc_planner.cpp"]
+SOURCES = ["nsgc_kernels.hip", "nsgc_sort.hip", "nsgc_large.hip", "nsgc_anon.hip", "nsgc_noalloc.hip",
+           "nsgc_api.cpp", "nsgc_planner.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

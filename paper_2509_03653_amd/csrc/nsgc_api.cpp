@@ -15,6 +15,8 @@
 #include <vector>
 
 #include "nsgc.h"
+#include "nsgc_anon.hpp"
+#include "nsgc_large.hpp"
 #include "nsgc_planner.hpp"
 
 namespace nsgc {
@@ -26,6 +28,8 @@ hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_bu
 hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
 hipError_t launch_order(const nsgc_dev_plan* P, hipStream_t s);
 hipError_t launch_finish(const nsgc_dev_plan* P, uint32_t grid, hipStream_t s);
+hipError_t launch_rowcol_ent(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
+size_t lds_rc_ent_bytes(uint32_t slots_log2);
 hipError_t launch_rowcol(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
 size_t lds_small_bytes(uint32_t slots_log2);
 size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2, uint32_t max_rc_buckets);
@@ -66,7 +70,7 @@ struct Slot {
   hipEvent_t ev[kStages] = {};
   bool ev_used[kStages] = {};
   int next = 0;
-  hipEvent_t phase_ev[5] = {};  // timing events of nsgc_window_stats_timed
+  hipEvent_t phase_ev[6] = {};  // timing events of nsgc_window_stats_timed
 };
 
 // State of the fixed-scratch form on one device: a host staging buffer for
@@ -187,9 +191,9 @@ int take_stage(Slot* sl, size_t need, hipStream_t s, int* idx) {
 }
 
 struct Launch {
-  uint32_t grid_small, grid_part, grid_link, grid_rc, grid_linkw, grid_finish;  // persistent grids
+  uint32_t grid_small, grid_part, grid_link, grid_rc, grid_linkw, grid_finish, grid_rce;  // persistent grids
   bool combine;                                        // phase-B emission combines per id
-  size_t lds_small, lds_part, lds_link, lds_rc, lds_linkw;
+  size_t lds_small, lds_part, lds_link, lds_rc, lds_linkw, lds_rce;
   uint32_t max_link_buckets, max_rc_buckets;
 };
 
@@ -234,6 +238,12 @@ int launch_params(DevCtx* c, const nsgc_tune& t, Launch* out) {
   // the workgroup kernels' 512-thread workgroups
   if ((rc = resident_cap(c, 5, tile, L.lds_linkw, 4 * want, &L.grid_linkw)) != NSGC_OK) return rc;
   L.grid_finish = uint32_t(c->cus) * 4;
+  // the entity outputs' phase C (two tables per workgroup)
+  L.lds_rce = lds_rc_ent_bytes(uint32_t(std::min(t.rc_slots_log2, 12)));
+  L.grid_rce = 0;
+  if (L.lds_rce <= c->lds_limit &&
+      (rc = resident_cap(c, 6, tile, L.lds_rce, want, &L.grid_rce)) != NSGC_OK)
+    return rc;
   *out = L;
   return NSGC_OK;
 }
@@ -250,9 +260,18 @@ int plan_variant(const HostPlan& hp) {
 // capture) every kernel of `variant` is launched with the full persistent
 // grid; otherwise grids are trimmed to the item counts and empty phases are
 // skipped.
+// The buffers the large-window tier works on directly (it takes no plan).
+struct LargeArgs {
+  const uint32_t* src;
+  const uint32_t* dst;
+  unsigned long long* out;   // nsgc_stats array
+  char* ws;                  // the workspace (its large-tier region per the plan's layout)
+  uint32_t grid;
+};
+
 int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch& L,
                     uint32_t tile_log2, hipStream_t s, bool fixed_grid, int variant,
-                    const hipEvent_t* ev = nullptr) {
+                    const hipEvent_t* ev = nullptr, const LargeArgs* la = nullptr) {
   auto grid = [&](uint32_t items, uint32_t cap) { return fixed_grid ? cap : std::min(items, cap); };
   auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
   const bool small = fixed_grid ? (variant & 1) != 0 : !hp.small.empty();
@@ -270,13 +289,25 @@ int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch
   if (linkw)
     NSGC_HIP(launch_links_wave(dplan, grid((hp.itemsBw + 3) / 4, L.grid_linkw), L.lds_linkw, s));
   if (linkb)
-    NSGC_HIP(launch_links(dplan, L.combine, L.max_rc_buckets, grid(hp.itemsBb, L.grid_link),
-                          L.lds_link, s));
+    NSGC_HIP(launch_links(dplan, L.combine && !hp.entity, L.max_rc_buckets,
+                          grid(hp.itemsBb, L.grid_link), L.lds_link, s));
   NSGC_HIP(mark(3));
-  if (part) NSGC_HIP(launch_order(dplan, s));
-  if (part) NSGC_HIP(launch_rowcol(dplan, grid(hp.itemsC, L.grid_rc), L.lds_rc, s));
+  if (part && hp.entity) {
+    NSGC_HIP(launch_rowcol_ent(dplan, grid(hp.itemsC, L.grid_rce), L.lds_rce, s));
+  } else if (part) {
+    NSGC_HIP(launch_order(dplan, s));
+    NSGC_HIP(launch_rowcol(dplan, grid(hp.itemsC, L.grid_rc), L.lds_rc, s));
+  }
   if (part) NSGC_HIP(launch_finish(dplan, grid(uint32_t(hp.win.size()), L.grid_finish), s));
   NSGC_HIP(mark(4));
+  if (!hp.large.empty()) {
+    if (!la) return NSGC_ERR_INTERNAL;
+    char* region = la->ws + hp.layout().large;
+    for (const LargeWindow& lw : hp.large)
+      NSGC_HIP(large_window_stats(la->src + lw.in_begin, la->dst + lw.in_begin, lw.n, region,
+                                  la->out + (unsigned long long)lw.out_index * 9, la->grid, s));
+  }
+  NSGC_HIP(mark(5));
   return NSGC_OK;
 }
 
@@ -321,12 +352,16 @@ int run_plan(DevCtx* c, Slot* sl, const HostPlan& hp, const nsgc_tune& t, const 
   NSGC_HIP(hipMemcpyAsync(sl->plan_dev, sl->stage[k], pbytes, hipMemcpyHostToDevice, s));
   NSGC_HIP(hipEventRecord(sl->ev[k], s));
   sl->ev_used[k] = true;
+  const LargeArgs la = {src, dst, static_cast<unsigned long long*>(out), sl->ws,
+                        uint32_t(c->cus) * 8};
   return enqueue_kernels(hp, reinterpret_cast<const nsgc_dev_plan*>(sl->plan_dev), L,
-                         hp.tile_log2, s, false, 0, ev);
+                         hp.tile_log2, s, false, 0, ev, &la);
 }
 
-// Upper bound of the workspace for any batch within the limits.
-size_t workspace_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune& t) {
+// Upper bound of the workspace for any batch within the limits (`large`: the
+// batch may use the large-window tier).
+size_t workspace_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune& t,
+                       bool large = true) {
   const uint64_t P = uint64_t(std::max<int64_t>(max_packets, 0));
   const uint64_t W = uint64_t(std::max<int64_t>(max_windows, 1));
   int lt = 1 << 30, rt = 1 << 30;
@@ -346,7 +381,11 @@ size_t workspace_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune
   const uint64_t items = std::min<uint64_t>(4 * P / uint64_t(rt) + 4 * W, 2 * W * MRC);
   // bucket totals: 16 B per phase-B and per phase-C item
   const uint64_t bitems = std::min<uint64_t>(2 * P / uint64_t(lt) + 2 * W, W * MB);
-  return size_t(P * 24 + (tilemeta + lbmeta + 2 * items) * 4 + (bitems + items) * 16 + 10 * 256);
+  size_t b = size_t(P * 24 + (tilemeta + lbmeta + 2 * items) * 4 + (bitems + items) * 16 + 10 * 256);
+  // a large window's region comes on top of the partitioned windows' regions
+  if (large && t.large_min_log2 < 33 && P >= (uint64_t(1) << t.large_min_log2))
+    b += large_window_bytes(P) + 256;
+  return b;
 }
 
 // The batched form (caller holds g_mu, arguments validated, num_windows > 0).
@@ -399,9 +438,11 @@ int plain_locked(const uint32_t* src, const uint32_t* dst, const int64_t* window
   NSGC_HIP(hipEventRecord(sl->ev[k], s));
   sl->ev_used[k] = true;
   for (int64_t w = 0; w < num_windows; ++w) {
+    const LargeArgs la = {src, dst, reinterpret_cast<unsigned long long*>(out_stats + w), sl->ws,
+                          uint32_t(c->cus) * 8};
     rc = enqueue_kernels(plans[size_t(w)],
                          reinterpret_cast<const nsgc_dev_plan*>(sl->plan_dev + at[size_t(w)]), L,
-                         plans[size_t(w)].tile_log2, s, false, 0);
+                         plans[size_t(w)].tile_log2, s, false, 0, nullptr, &la);
     if (rc != NSGC_OK) return rc;
   }
   return NSGC_OK;
@@ -476,8 +517,10 @@ int run_fixed_scratch(const uint32_t* src, const uint32_t* dst, const int64_t* w
   if (f.used && f.last_stream != s) NSGC_HIP(hipStreamWaitEvent(s, f.done, 0));
   NSGC_HIP(hipMemcpyAsync(plan_dev, f.stage.data(), pbytes, hipMemcpyHostToDevice, s));
   NSGC_HIP(hipEventRecord(f.copied, s));
+  const LargeArgs la = {src, dst, reinterpret_cast<unsigned long long*>(out_stats), ws,
+                        uint32_t(c->cus) * 8};
   rc = enqueue_kernels(hp, reinterpret_cast<const nsgc_dev_plan*>(plan_dev), L, hp.tile_log2, s,
-                       false, 0);
+                       false, 0, nullptr, &la);
   if (rc != NSGC_OK) return rc;
   NSGC_HIP(hipEventRecord(f.done, s));
   f.last_stream = s;
@@ -532,6 +575,98 @@ int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
   return plain_locked(src, dst, window_offsets, num_windows, out_stats, s);
 }
 
+namespace {
+
+// Host offsets of one entity list: num_windows + 1 non-decreasing values >= 0.
+int check_list_offsets(const int64_t* off, int64_t num_windows, const void* list) {
+  if (!off) return NSGC_ERR_INVALID_ARG;
+  if (off[0] < 0) return NSGC_ERR_BAD_OFFSETS;
+  for (int64_t w = 0; w < num_windows; ++w)
+    if (off[w + 1] < off[w]) return NSGC_ERR_BAD_OFFSETS;
+  if (off[num_windows] > off[0] && !list) return NSGC_ERR_INVALID_ARG;
+  return NSGC_OK;
+}
+
+int entities_call(const uint32_t* src, const uint32_t* dst, const int64_t* window_offsets,
+                  int64_t num_windows, const int64_t* const* list_off, void* const* lists,
+                  nsgc_entity_counts* counts, void* stream) {
+  int rc = validate_common(src, dst, window_offsets, num_windows, counts);
+  if (rc != NSGC_OK || num_windows == 0) return rc;
+  if (list_off)
+    for (int k = 0; k < 3; ++k)
+      if ((rc = check_list_offsets(list_off[k], num_windows, lists[k])) != NSGC_OK) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
+  std::lock_guard<std::mutex> lock(g_mu);
+  nsgc_tune t = current_tune();
+  t.combine_probes = 0;                                // links are listed by the per-link emission
+  t.rc_slots_log2 = std::min(t.rc_slots_log2, 12);     // two phase-C tables per workgroup
+  HostPlan hp;
+  if ((rc = make_plan(window_offsets, num_windows, t, &hp, true)) != NSGC_OK) return rc;
+  hp.ent_cur.assign(size_t(num_windows) * 3, 0);
+  hp.ent_end.assign(size_t(num_windows) * 3, 0);
+  if (list_off) {
+    for (int64_t w = 0; w < num_windows; ++w)
+      for (int k = 0; k < 3; ++k) {
+        hp.ent_cur[size_t(w) * 3 + k] = uint64_t(list_off[k][w]);
+        hp.ent_end[size_t(w) * 3 + k] = uint64_t(list_off[k][w + 1]);
+      }
+    hp.ent_links = lists[0];
+    hp.ent_src = lists[1];
+    hp.ent_dst = lists[2];
+  }
+  hp.ent_counts = counts;
+  DevCtx* c = nullptr;
+  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
+  Slot* sl = nullptr;
+  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
+  Launch L;
+  if ((rc = launch_params(c, t, &L)) != NSGC_OK) return rc;
+  if (!hp.win.empty() && L.grid_rce == 0) return NSGC_ERR_INVALID_ARG;
+  return run_plan(c, sl, hp, t, src, dst, nullptr, s);
+}
+
+}  // namespace
+
+int nsgc_window_entity_counts(const uint32_t* src, const uint32_t* dst,
+                              const int64_t* window_offsets, int64_t num_windows,
+                              nsgc_entity_counts* counts, void* stream) {
+  return entities_call(src, dst, window_offsets, num_windows, nullptr, nullptr, counts, stream);
+}
+
+int nsgc_window_entities(const uint32_t* src, const uint32_t* dst,
+                         const int64_t* window_offsets, int64_t num_windows,
+                         const int64_t* link_offsets, int64_t* links,
+                         const int64_t* source_offsets, int64_t* sources,
+                         const int64_t* destination_offsets, int64_t* destinations,
+                         nsgc_entity_counts* counts, void* stream) {
+  const int64_t* offs[3] = {link_offsets, source_offsets, destination_offsets};
+  void* lists[3] = {links, sources, destinations};
+  return entities_call(src, dst, window_offsets, num_windows, offs, lists, counts, stream);
+}
+
+int nsgc_anonymize(const uint32_t* src, const uint32_t* dst, int64_t num_packets, uint64_t seed,
+                   uint32_t* anon_src, uint32_t* anon_dst, uint64_t* num_addresses, void* stream) {
+  if (num_packets < 0 || num_packets >= (int64_t(1) << 31)) return NSGC_ERR_INVALID_ARG;
+  if (!num_addresses || reinterpret_cast<uintptr_t>(num_addresses) % 8 != 0)
+    return NSGC_ERR_INVALID_ARG;
+  if (num_packets > 0 && (!src || !dst || !anon_src || !anon_dst)) return NSGC_ERR_INVALID_ARG;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
+  std::lock_guard<std::mutex> lock(g_mu);
+  DevCtx* c = nullptr;
+  int rc;
+  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
+  Slot* sl = nullptr;
+  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
+  const unsigned long long n = (unsigned long long)num_packets;
+  if ((rc = ensure_device(&sl->ws, &sl->ws_cap, anonymize_bytes(n), s)) != NSGC_OK) return rc;
+  NSGC_HIP(anonymize(src, dst, n, seed, anon_src, anon_dst,
+                     reinterpret_cast<unsigned long long*>(num_addresses), sl->ws,
+                     uint32_t(c->cus) * 8, s));
+  return NSGC_OK;
+}
+
 int nsgc_set_plain_mode(int on) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_plain_mode = on != 0;
@@ -549,7 +684,7 @@ int nsgc_window_stats_timed(const uint32_t* src, const uint32_t* dst,
   if (!phase_ms) return NSGC_ERR_INVALID_ARG;
   int rc = validate_common(src, dst, window_offsets, num_windows, out_stats);
   if (rc != NSGC_OK) return rc;
-  for (int i = 0; i < 4; ++i) phase_ms[i] = 0.0f;
+  for (int i = 0; i < 5; ++i) phase_ms[i] = 0.0f;
   if (num_windows == 0) return NSGC_OK;
   std::lock_guard<std::mutex> lock(g_mu);
   const nsgc_tune t = current_tune();
@@ -561,11 +696,11 @@ int nsgc_window_stats_timed(const uint32_t* src, const uint32_t* dst,
   if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
   Slot* sl = nullptr;
   if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < 6; ++i)
     if (!sl->phase_ev[i]) NSGC_HIP(hipEventCreate(&sl->phase_ev[i]));
   if ((rc = run_plan(c, sl, hp, t, src, dst, out_stats, s, sl->phase_ev)) != NSGC_OK) return rc;
-  NSGC_HIP(hipEventSynchronize(sl->phase_ev[4]));
-  for (int i = 0; i < 4; ++i)
+  NSGC_HIP(hipEventSynchronize(sl->phase_ev[5]));
+  for (int i = 0; i < 5; ++i)
     NSGC_HIP(hipEventElapsedTime(&phase_ms[i], sl->phase_ev[i], sl->phase_ev[i + 1]));
   return NSGC_OK;
 }
@@ -597,7 +732,7 @@ int nsgc_release(void) {
       if (sl->stage[k]) (void)hipHostFree(sl->stage[k]);
       if (sl->ev[k]) (void)hipEventDestroy(sl->ev[k]);
     }
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < 6; ++k)
       if (sl->phase_ev[k]) (void)hipEventDestroy(sl->phase_ev[k]);
     delete sl;
   }
@@ -796,7 +931,8 @@ int nsgc_graph_create(int64_t max_packets, int64_t max_windows, nsgc_graph** out
       return hip_fail(e);
     }
   }
-  if ((rc = ensure_device(&g->ws, &g->ws_cap, workspace_bound(max_packets, max_windows, g->tune),
+  if ((rc = ensure_device(&g->ws, &g->ws_cap,
+                          workspace_bound(max_packets, max_windows, g->tune, false),
                           g->capture)) != NSGC_OK) {
     destroy_graph(g);
     return rc;
@@ -818,8 +954,9 @@ int nsgc_graph_launch(nsgc_graph* g, const uint32_t* src, const uint32_t* dst,
   int dev = 0;
   NSGC_HIP(hipGetDevice(&dev));
   if (dev != g->device) return NSGC_ERR_INVALID_ARG;
-  HostPlan hp;
-  if ((rc = make_plan(window_offsets, num_windows, g->tune, &hp)) != NSGC_OK) return rc;
+  HostPlan hp;   // a captured graph has no large-window tier (its launches are fixed)
+  if ((rc = make_plan(window_offsets, num_windows, g->tune, &hp, false, false)) != NSGC_OK)
+    return rc;
   if (hp.plan_bytes() > g->inst[0].plan_cap) return NSGC_ERR_INTERNAL;
   const size_t need = hp.layout().total;
   if (need > g->ws_cap) {

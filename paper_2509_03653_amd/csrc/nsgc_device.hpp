@@ -98,13 +98,37 @@ __device__ __forceinline__ uint32_t col_hash(uint32_t x) {
   return x;
 }
 
+// Inverse of an odd multiplier modulo 2^32 (Newton's iteration doubles the
+// correct low bits each step: 3 -> 6 -> 12 -> 24 -> 48).
+constexpr uint32_t odd_inverse(uint32_t m) {
+  uint32_t x = m;   // correct to 3 bits for odd m
+  for (int i = 0; i < 4; ++i) x *= 2u - m * x;
+  return x;
+}
+static_assert(0x897EA68Du * odd_inverse(0x897EA68Du) == 1u, "multiplier inverse");
+static_assert(0x3EA9E261u * odd_inverse(0x3EA9E261u) == 1u, "multiplier inverse");
+
+// row_hash^-1: the steps of row_hash undone in reverse order (x ^= x >> 16
+// is its own inverse on 32 bits; x ^= x >> 15 is undone by x ^= x >> 15 ^ x >> 30).
+__device__ __forceinline__ uint32_t row_unhash(uint32_t x) {
+  x ^= x >> 16;
+  x *= odd_inverse(0x3EA9E261u);
+  x ^= (x >> 15) ^ (x >> 30);
+  x *= odd_inverse(0x897EA68Du);
+  x ^= x >> 16;
+  x ^= 0x421E9A93u;
+  return x;
+}
+
 __device__ __forceinline__ uint32_t rotl32(uint32_t x, uint32_t r) {
   return (x << r) | (x >> (32u - r));
 }
 
-// The hashed link key of packet (s, d).
-__device__ __forceinline__ u64 link_key(uint32_t s, uint32_t d) {
-  return (u64(row_hash(s)) << 32) | col_hash(d);
+// The hashed link key of packet (s, d).  With `same` (the entity outputs,
+// which need sources and destinations in one hashed space to count their
+// union) the destination is hashed like a source.
+__device__ __forceinline__ u64 link_key(uint32_t s, uint32_t d, bool same = false) {
+  return (u64(row_hash(s)) << 32) | (same ? row_hash(d) : col_hash(d));
 }
 
 // Position bits of a hashed link key: the link bucket is the top bits, the

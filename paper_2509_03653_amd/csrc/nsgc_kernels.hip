@@ -118,6 +118,47 @@ __device__ __forceinline__ void write_entry(NSGC_GLOBAL u64* e, uint32_t at, uin
   }
 }
 
+// ---- entity outputs ------------------------------------------------------
+// Rows of the caller's lists: the lanes with `want` reserve consecutive rows
+// of list `which` (0 links, 1 sources, 2 destinations) of window w with one
+// 64-bit atomic per wavefront; a row at or past the window's end is not
+// written (the window's count still reports every entity).
+__device__ __forceinline__ u64 ent_reserve(const nsgc_dev_plan* P, uint32_t w, int which,
+                                           bool want) {
+  const u64 m = __ballot(want);
+  if (m == 0) return ~0ull;
+  const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+  u64 base = 0;
+  if (int(lane_id()) == leader)
+    base = __hip_atomic_fetch_add(P->ent_cur + u64(w) * 3 + which, u64(__popcll(m)),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const u64 b = (u64(readlane(uint32_t(base >> 32), leader)) << 32) | readlane(uint32_t(base), leader);
+  return b + rank_below(m);
+}
+
+__device__ __forceinline__ void ent_row(const nsgc_dev_plan* P, long long* list, uint32_t w,
+                                        int which, u64 row, u64 a, u64 b, u64 c) {
+  if (row < P->ent_end[u64(w) * 3 + which]) {
+    NSGC_GLOBAL long long* r = gptr(list) + row * 3;
+    r[0] = (long long)a;
+    r[1] = (long long)b;
+    r[2] = (long long)c;
+  }
+}
+
+// Find a 32-bit id in an open-addressing LDS table filled by cas_insert
+// (probing from id & mask): true if present.
+__device__ __forceinline__ bool lds_find32(const uint32_t* tk, uint32_t mask, uint32_t id) {
+  uint32_t s = id & mask;
+  for (uint32_t p = 0; p <= mask; ++p) {
+    const uint32_t cur = tk[s];
+    if (cur == id) return true;
+    if (cur == EMPTY32) return false;
+    s = (s + 1) & mask;
+  }
+  return false;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -186,7 +227,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {   // hashed identities (see link_key)
         s[u] = row_hash(s[u]);
-        d[u] = col_hash(d[u]);
+        d[u] = P->entity ? row_hash(d[u]) : col_hash(d[u]);
         key[u] = (u64(s[u]) << 32) | d[u];
         h[u] = uint32_t(link_pos(key[u]));
         // the key equal to the empty marker is counted outside the table
@@ -266,6 +307,59 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
       o[3] = bad ? ~0ull : nr; o[4] = bad ? ~0ull : mr; o[5] = bad ? ~0ull : mf;
       o[6] = bad ? ~0ull : nc; o[7] = bad ? ~0ull : mc; o[8] = bad ? ~0ull : mg;
     }
+    if (P->entity) {
+      // the lists, and the sources and destinations counted once in their union
+      // (destinations are hashed like sources in entity mode)
+      const uint32_t w = D.out_index;
+      uint32_t uni = 0;
+      for (uint32_t i0 = 0; i0 < S; i0 += NSGC_BLOCK) {
+        const uint32_t i = i0 + threadIdx.x;
+        const bool l = i < S && lk[i] != EMPTY64;
+        const bool r = i < S && rk[i] != EMPTY32;
+        const bool c = i < S && ck[i] != EMPTY32;
+        if (c && !lds_find32(rk, S - 1, ck[i])) ++uni;
+        if (P->ent_links) {
+          const u64 row = ent_reserve(P, w, 0, l);
+          if (l) ent_row(P, P->ent_links, w, 0, row, row_unhash(uint32_t(lk[i] >> 32)),
+                         row_unhash(uint32_t(lk[i])), lc[i]);
+        }
+        if (P->ent_src) {
+          const u64 row = ent_reserve(P, w, 1, r);
+          if (r) ent_row(P, P->ent_src, w, 1, row, row_unhash(rk[i]), rp[i], rf[i]);
+        }
+        if (P->ent_dst) {
+          const u64 row = ent_reserve(P, w, 2, c);
+          if (c) ent_row(P, P->ent_dst, w, 2, row, row_unhash(ck[i]), cp[i], cf[i]);
+        }
+      }
+      if (threadIdx.x == 0) {   // the hashed id EMPTY32 lives outside the tables
+        const uint32_t xe = row_unhash(EMPTY32);
+        if (misc[0] && P->ent_links) {
+          const u64 row = __hip_atomic_fetch_add(P->ent_cur + u64(w) * 3, 1ull, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          ent_row(P, P->ent_links, w, 0, row, xe, xe, misc[0]);
+        }
+        if (misc[2] && P->ent_src) {
+          const u64 row = __hip_atomic_fetch_add(P->ent_cur + u64(w) * 3 + 1, 1ull,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ent_row(P, P->ent_src, w, 1, row, xe, misc[2], misc[3]);
+        }
+        if (misc[4] && P->ent_dst) {
+          const u64 row = __hip_atomic_fetch_add(P->ent_cur + u64(w) * 3 + 2, 1ull,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ent_row(P, P->ent_dst, w, 2, row, xe, misc[4], misc[5]);
+        }
+        if (misc[4] && !misc[2]) ++uni;
+      }
+      uni = block_sum(uni, red);
+      if (threadIdx.x == 0) {
+        NSGC_GLOBAL long long* cnt = gptr(P->ent_counts) + u64(w) * 4;
+        cnt[0] = (long long)nl;
+        cnt[1] = (long long)nr;
+        cnt[2] = (long long)nc;
+        cnt[3] = (long long)(nr + uni);
+      }
+    }
     q.stage_next(items);
     __syncthreads();
   }
@@ -299,6 +393,7 @@ __global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restric
   // packets per row and column bucket of a window's first tile; in the staging
   // area, which is free until the bucket scan's barriers
   uint32_t* rch = reinterpret_cast<uint32_t*>(stage);
+  const bool same = P->entity != 0;   // entity outputs: destinations hashed like sources
   const uint32_t items = P->itemsA;
   for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
     const uint32_t wi = owner_of_wave(gptr(P->prefA), P->num_part, item);
@@ -335,10 +430,10 @@ __global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restric
         const uint32_t idx = (k * NT + threadIdx.x) * 4;
         const v4u32 s4 = *(const NSGC_GLOBAL v4u32*)(src + idx);
         const v4u32 d4 = *(const NSGC_GLOBAL v4u32*)(dst + idx);
-        key[4 * k + 0] = link_key(s4.x, d4.x);
-        key[4 * k + 1] = link_key(s4.y, d4.y);
-        key[4 * k + 2] = link_key(s4.z, d4.z);
-        key[4 * k + 3] = link_key(s4.w, d4.w);
+        key[4 * k + 0] = link_key(s4.x, d4.x, same);
+        key[4 * k + 1] = link_key(s4.y, d4.y, same);
+        key[4 * k + 2] = link_key(s4.z, d4.z, same);
+        key[4 * k + 3] = link_key(s4.w, d4.w, same);
         ok[4 * k + 0] = ok[4 * k + 1] = ok[4 * k + 2] = ok[4 * k + 3] = true;
       }
     } else {
@@ -346,7 +441,7 @@ __global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restric
       for (int k = 0; k < PER; ++k) {
         const uint32_t idx = k * NT + threadIdx.x;
         ok[k] = idx < len;
-        key[k] = ok[k] ? link_key(src[idx], dst[idx]) : 0ull;
+        key[k] = ok[k] ? link_key(src[idx], dst[idx], same) : 0ull;
       }
     }
 #pragma unroll
@@ -797,9 +892,24 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
             write_entry(ec, ac[u], uint32_t(key[u]), cnt[u], 1, parts);
           }
         }
+        if (P->ent_links) {   // entity outputs: the links themselves
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const u64 row = ent_reserve(P, W.out_index, 0, ok[u]);
+            if (ok[u])
+              ent_row(P, P->ent_links, W.out_index, 0, row, row_unhash(uint32_t(key[u] >> 32)),
+                      row_unhash(uint32_t(key[u])), cnt[u]);
+          }
+        }
       });
       if (threadIdx.x == 0 && misc[1]) {
         const uint32_t c = misc[1];
+        if (P->ent_links) {
+          const uint32_t xe = row_unhash(EMPTY32);
+          const u64 row = __hip_atomic_fetch_add(P->ent_cur + u64(W.out_index) * 3, 1ull,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ent_row(P, P->ent_links, W.out_index, 0, row, xe, xe, c);
+        }
         const uint32_t parts = entry_parts(c, 1);
         write_entry(er, lds_add(&histR[top32(EMPTY32, W.logR)], parts), EMPTY32, c, 1,
                     parts);
@@ -1285,8 +1395,19 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P) {
         const uint32_t ac = lds_add(&histC[top32(uint32_t(key), W.logC)], parts);
         write_entry(er, ar, uint32_t(key >> 32), cnt, 1, parts);
         write_entry(ec, ac, uint32_t(key), cnt, 1, parts);
+        if (P->ent_links) {   // entity outputs: the links themselves
+          const u64 row = ent_reserve(P, W.out_index, 0, true);
+          ent_row(P, P->ent_links, W.out_index, 0, row, row_unhash(uint32_t(key >> 32)),
+                  row_unhash(uint32_t(key)), cnt);
+        }
       }
       if (lane == 0 && special) {
+        if (P->ent_links) {
+          const uint32_t xe = row_unhash(EMPTY32);
+          const u64 row = __hip_atomic_fetch_add(P->ent_cur + u64(W.out_index) * 3, 1ull,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ent_row(P, P->ent_links, W.out_index, 0, row, xe, xe, special);
+        }
         const uint32_t parts = entry_parts(special, 1);
         write_entry(er, lds_add(&histR[top32(EMPTY32, W.logR)], parts), EMPTY32, special, 1, parts);
         write_entry(ec, lds_add(&histC[top32(EMPTY32, W.logC)], parts), EMPTY32, special, 1, parts);
@@ -1625,6 +1746,216 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
 }
 
 // ---------------------------------------------------------------------------
+// Phase C for the entity outputs: item b of a window aggregates row bucket b
+// and column bucket b together (in entity mode destinations are hashed like
+// sources and R = C, so both buckets cover the same hashed addresses).  Two
+// LDS tables, one per view, give the bucket totals as in k_rowcol, the rows
+// of the source and destination lists, and the bucket's share of the union
+// |sources U destinations|: its sources plus its destinations that are not
+// also sources.  Overflow sweeps split both views by the same id bits.  The
+// lists are written only by a pass whose sweeps all fit: a single sweep
+// writes as it goes; with more sweeps, a second pass over the final sweeps
+// writes after a first one has found how many are needed.  The column
+// positions of the queue have no work of their own.
+// ---------------------------------------------------------------------------
+
+size_t lds_rc_ent_bytes(uint32_t slots_log2) {
+  const size_t S = size_t(1) << slots_log2;
+  return align16(S * 4) * 6 + 256;
+}
+
+__global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol_ent(nsgc_dev_plan* P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t S = 1u << P->rc_slots_log2;
+  unsigned char* p = smem;
+  uint32_t* tkv[2];
+  uint32_t* tav[2];
+  uint32_t* tbv[2];
+  for (int v = 0; v < 2; ++v) {
+    tkv[v] = reinterpret_cast<uint32_t*>(p);  p += align16(S * 4);
+    tav[v] = reinterpret_cast<uint32_t*>(p);  p += align16(S * 4);
+    tbv[v] = reinterpret_cast<uint32_t*>(p);  p += align16(S * 4);
+  }
+  uint32_t* misc = reinterpret_cast<uint32_t*>(p);   // [0] fail flag, [2,3] special row,
+                                                     // [4,5] special column, [7] queue slot
+  uint32_t* red = misc + 8;
+
+  for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
+    for (int v = 0; v < 2; ++v) {
+      tkv[v][i] = EMPTY32;
+      tav[v][i] = 0;
+      tbv[v][i] = 0;
+    }
+  }
+
+  const uint32_t items = P->itemsC;
+  ItemQueue q(gptr(&P->queue[2][0]), misc + 7, NSGC_QCLASSES);
+  for (uint32_t item = q.first(items); item != NO_ITEM; item = q.read()) {
+    const uint32_t it = uniform(item);
+    const uint32_t wi = sload(P->itemwinC + it);
+    const nsgc_win_desc W = sload_words(P->win + wi);
+    const uint32_t k = it - sload(P->prefC + wi);
+    const uint32_t B = 1u << W.logB, R = 1u << W.logR;
+    if (k >= R) {   // a column position: handled with row item k - R
+      q.stage_next(items);
+      __syncthreads();
+      continue;
+    }
+    const uint32_t w = W.out_index;
+    const uint32_t logK = W.logR;
+    const NSGC_GLOBAL uint32_t* rec = gptr(P->lbmeta) + W.lbmeta;
+
+    // Table of view v (0 rows, 1 columns) for sweep sw of 2^logS.
+    auto build = [&](int v, uint32_t logS, uint32_t sw) {
+      const NSGC_GLOBAL uint32_t* st0 = rec + B + (v == 0 ? u64(k) * B : u64(R + 1) * B + u64(k) * B);
+      const NSGC_GLOBAL uint32_t* st1 = st0 + B;
+      const NSGC_GLOBAL u64* em = gptr(v == 0 ? P->emit_row : P->emit_col) + W.ws;
+      uint32_t* tk = tkv[v];
+      uint32_t* ta = tav[v];
+      uint32_t* tb = tbv[v];
+      uint32_t* spc = misc + 2 + 2 * v;
+      auto seg = [&](uint32_t lb, u64& base, uint32_t& len) {
+        const uint32_t s0 = st0[lb], s1 = st1[lb];
+        base = u64(rec[lb]) + s0;
+        len = s1 - s0;
+      };
+      gather_by_wave<RC_MAXU>(B, seg, [&](const auto& pos, const auto& okin) {
+        constexpr int U = array_len<decltype(pos)>();
+        uint32_t id[U], h[U], pk[U], ln[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const u64 ee = em[okin[u] ? pos[u] : 0ull];   // position 0 exists; masked below
+          const u64 e = okin[u] ? ee : 0ull;
+          id[u] = uint32_t(e >> 32);
+          pk[u] = uint32_t(e) & ENT_PMAX;
+          ln[u] = uint32_t(e) >> NSGC_ENT_PACKET_BITS;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          h[u] = id[u];
+          ok[u] = okin[u] && !(logS && next32(h[u], logK, logS) != sw);
+          if (ok[u] && id[u] == EMPTY32) {
+            lds_add(&spc[0], pk[u]);
+            lds_add(&spc[1], ln[u]);
+            ok[u] = false;
+          }
+        }
+        int slot[U];
+        bool fresh[U];
+        if (!cas_insert<U>(tk, S - 1, id, h, ok, slot, fresh, NSGC_MAX_PROBES))
+          lds_store(&misc[0], 1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (slot[u] >= 0) {
+            lds_add(&ta[slot[u]], pk[u]);
+            lds_add(&tb[slot[u]], ln[u]);
+          }
+        }
+        (void)fresh;
+      });
+    };
+
+    // One pass over both tables: the totals (when `stats`), the list rows
+    // and the union share (when `write`), and emptying the tables.
+    uint32_t nr = 0, mr = 0, mf = 0, nc = 0, mc = 0, mg = 0, uni = 0;
+    auto harvest = [&](bool stats, bool write) {
+      for (uint32_t i0 = 0; i0 < S; i0 += NSGC_BLOCK) {
+        const uint32_t i = i0 + threadIdx.x;
+        const uint32_t rid = tkv[0][i], cid = tkv[1][i];
+        const bool r = rid != EMPTY32, c = cid != EMPTY32;
+        if (stats) {
+          if (r) { ++nr; mr = max(mr, tav[0][i]); mf = max(mf, tbv[0][i]); }
+          if (c) { ++nc; mc = max(mc, tav[1][i]); mg = max(mg, tbv[1][i]); }
+        }
+        if (write) {
+          if (r) ++uni;
+          if (c && !lds_find32(tkv[0], S - 1, cid)) ++uni;
+          if (P->ent_src) {
+            const u64 row = ent_reserve(P, w, 1, r);
+            if (r) ent_row(P, P->ent_src, w, 1, row, row_unhash(rid), tav[0][i], tbv[0][i]);
+          }
+          if (P->ent_dst) {
+            const u64 row = ent_reserve(P, w, 2, c);
+            if (c) ent_row(P, P->ent_dst, w, 2, row, row_unhash(cid), tav[1][i], tbv[1][i]);
+          }
+        }
+      }
+      if (threadIdx.x == 0) {   // the hashed id EMPTY32 lives outside the tables
+        if (stats) {
+          if (misc[3]) { ++nr; mr = max(mr, misc[2]); mf = max(mf, misc[3]); }
+          if (misc[5]) { ++nc; mc = max(mc, misc[4]); mg = max(mg, misc[5]); }
+        }
+        if (write) {
+          const uint32_t xe = row_unhash(EMPTY32);
+          if (misc[3] || misc[5]) ++uni;
+          if (misc[3] && P->ent_src) {
+            const u64 row = __hip_atomic_fetch_add(P->ent_cur + u64(w) * 3 + 1, 1ull,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ent_row(P, P->ent_src, w, 1, row, xe, misc[2], misc[3]);
+          }
+          if (misc[5] && P->ent_dst) {
+            const u64 row = __hip_atomic_fetch_add(P->ent_cur + u64(w) * 3 + 2, 1ull,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ent_row(P, P->ent_dst, w, 2, row, xe, misc[4], misc[5]);
+          }
+        }
+      }
+      __syncthreads();   // lookups done before the tables are emptied
+      for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
+        for (int v = 0; v < 2; ++v) {
+          tkv[v][i] = EMPTY32;
+          tav[v][i] = 0;
+          tbv[v][i] = 0;
+        }
+      }
+      __syncthreads();
+    };
+
+    auto sweep = [&](uint32_t logS, uint32_t sw) -> bool {
+      if (threadIdx.x < 6) misc[threadIdx.x] = 0;
+      __syncthreads();
+      build(0, logS, sw);
+      build(1, logS, sw);   // ends with a barrier
+      return misc[0] == 0;
+    };
+
+    bool abandoned = false;
+    uint32_t logS = 0;
+    for (;; ++logS) {   // the totals, and the lists when a single sweep fits
+      if (logS > P->max_sweeps_log2) { abandoned = true; break; }
+      nr = mr = mf = nc = mc = mg = uni = 0;
+      bool failed = false;
+      for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
+        if (!sweep(logS, sw)) { failed = true; harvest(false, false); break; }
+        harvest(true, logS == 0);
+      }
+      if (!failed) break;
+    }
+    if (!abandoned && logS > 0)   // the lists over the sweeps now known to fit
+      for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
+        sweep(logS, sw);
+        harvest(false, true);
+      }
+    uint32_t zero = 0;
+    block_sum_max2_to0(nr, mr, mf, red);
+    __syncthreads();
+    block_sum_max2_to0(nc, mc, mg, red);
+    __syncthreads();
+    block_sum_max2_to0(uni, zero, zero, red);
+    if (threadIdx.x == 0) {
+      const v4u32 pr = {nr, mr, mf, abandoned ? 1u : 0u};
+      const v4u32 pc = {nc, mc, mg, abandoned ? 1u : 0u};
+      gptr(reinterpret_cast<v4u32*>(P->partC))[it] = pr;
+      gptr(reinterpret_cast<v4u32*>(P->partC))[it + R] = pc;
+      gptr(P->partU)[it] = uni;
+    }
+    q.stage_next(items);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Per-window statistics of the partitioned windows from the bucket totals of
 // phases B and C: stats 0-2 sum / sum / max over the link buckets, 3-5 and
 // 6-8 count / max / max over the row and the column buckets.  Buckets
@@ -1636,7 +1967,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
 __global__ __launch_bounds__(256) void k_finish(nsgc_dev_plan* P) {
   // per wavefront: link sum, link count, row count, column count; maxima of
   // link packets, row packets, fan-out, column packets, fan-in; invalid flag
-  __shared__ uint32_t red[4][10];
+  __shared__ uint32_t red[4][11];   // [0][10]: the window's union count (entity mode)
   const uint32_t tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
   for (uint32_t wi = blockIdx.x; wi < P->num_part; wi += gridDim.x) {
     const nsgc_win_desc W = gload(P->win + wi);
@@ -1660,20 +1991,36 @@ __global__ __launch_bounds__(256) void k_finish(nsgc_dev_plan* P) {
       v[row ? 6 : 8] = max(v[row ? 6 : 8], x.z);
       v[9] |= x.w;
     }
+    uint32_t uni = 0;
+    if (P->entity) {
+      const NSGC_GLOBAL uint32_t* pu = gptr(P->partU) + gptr(P->prefC)[wi];
+      for (uint32_t i = tid; i < R; i += 256) uni += pu[i];
+      uni = wave_sum(uni);
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
 #pragma unroll
     for (int k = 4; k < 10; ++k) v[k] = wave_max(v[k]);
-    if (lane == 0)
+    if (lane == 0) {
 #pragma unroll
       for (int k = 0; k < 10; ++k) red[wv][k] = v[k];
+      red[wv][10] = uni;
+    }
     __syncthreads();
+    if (tid == 0) red[0][10] += red[1][10] + red[2][10] + red[3][10];
     if (tid == 0) {
       uint32_t t[10];
 #pragma unroll
       for (int k = 0; k < 10; ++k) {
         t[k] = red[0][k];
         for (int q = 1; q < 4; ++q) t[k] = k < 4 ? t[k] + red[q][k] : max(t[k], red[q][k]);
+      }
+      if (P->entity) {
+        NSGC_GLOBAL long long* cnt = gptr(P->ent_counts) + u64(W.out_index) * 4;
+        cnt[0] = (long long)t[1];
+        cnt[1] = (long long)t[2];
+        cnt[2] = (long long)t[3];
+        cnt[3] = (long long)red[0][10];
       }
       NSGC_GLOBAL u64* o = gptr(P->out) + u64(W.out_index) * 9;
       o[0] = u64(t[0]) | (t[9] ? NSGC_INVALID_BIT : 0ull);
@@ -1727,6 +2074,11 @@ hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t grid, size_t lds, 
   return hipGetLastError();
 }
 
+hipError_t launch_rowcol_ent(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(k_rowcol_ent, dim3(grid), dim3(NSGC_BLOCK), lds, s, const_cast<nsgc_dev_plan*>(P));
+  return hipGetLastError();
+}
+
 hipError_t launch_finish(const nsgc_dev_plan* P, uint32_t grid, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(grid), dim3(256), 0, s, const_cast<nsgc_dev_plan*>(P));
   return hipGetLastError();
@@ -1759,6 +2111,7 @@ hipError_t resident_blocks(int which, uint32_t tile_log2, size_t lds, int* block
     case 4: f = reinterpret_cast<const void*>(&k_links<true>); break;
     case 3: f = reinterpret_cast<const void*>(&k_rowcol); break;
     case 5: f = reinterpret_cast<const void*>(&k_links_wave); break;
+    case 6: f = reinterpret_cast<const void*>(&k_rowcol_ent); break;
     default: return hipErrorInvalidValue;
   }
   const int threads = which == 1 && tile_log2 == 14 ? NSGC_BLOCK * PART14_SCALE
@@ -1772,6 +2125,7 @@ hipError_t allow_large_lds(size_t bytes) {
   const void* fns[] = {
       reinterpret_cast<const void*>(&k_small),         reinterpret_cast<const void*>(&k_links<false>),
       reinterpret_cast<const void*>(&k_links<true>),   reinterpret_cast<const void*>(&k_links_wave),
+      reinterpret_cast<const void*>(&k_rowcol_ent),
       reinterpret_cast<const void*>(&k_rowcol),        reinterpret_cast<const void*>(&k_partition<4>),
       reinterpret_cast<const void*>(&k_partition<8>),  reinterpret_cast<const void*>(&k_partition<16>),
       reinterpret_cast<const void*>(&k_partition<32 / PART14_SCALE, NSGC_BLOCK * PART14_SCALE>)};

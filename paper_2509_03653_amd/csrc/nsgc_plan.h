@@ -27,8 +27,9 @@
 //     C  row / column aggregation: one item per row bucket and per column
 //        bucket gathers its runs from every link bucket into an LDS table
 //        id -> (packets, links), giving stats 3-5 and 6-8.
-//   Partial results of B and C combine into the window's output with 64-bit
-//   atomic add (counts) and max (maxima): exact and order-independent.
+//   Every phase-B and phase-C item stores its bucket's totals (counts and
+//   maxima); k_finish combines them per window by sums and maxima, which is
+//   exact because buckets partition the links, sources and destinations.
 #ifndef NSGC_PLAN_H_
 #define NSGC_PLAN_H_
 
@@ -123,6 +124,18 @@ struct nsgc_dev_plan {          // header of the device plan buffer
   uint32_t max_sweeps_log2;     // overflow sweeps allowed before a bucket is abandoned
   uint32_t combine_probes;      // 0: per-link emission; else probe limit of the combining table
   uint32_t order_items;         // 1: phase C takes its items in the order of `order`
+  // Entity outputs (zero / null for the statistics entry points).  In entity
+  // mode destinations are hashed like sources, row and column buckets
+  // coincide (R = C), and each phase-C row item also aggregates the column
+  // bucket of the same index, so that it can count the union of the two.
+  uint32_t entity;
+  long long* ent_links;         // rows (src, dst, packets), or null
+  long long* ent_src;           // rows (s, r(s), f(s)), or null
+  long long* ent_dst;           // rows (d, c(d), g(d)), or null
+  unsigned long long* ent_cur;  // [windows][3] next free row of each list
+  const unsigned long long* ent_end;  // [windows][3] end of each window's rows
+  long long* ent_counts;        // [windows][4] nsgc_entity_counts
+  uint32_t* partU;              // [itemsC] union count of each merged phase-C item
   // Work-queue counters of the small, B (workgroup), C and B (wavefront)
   // kernels.  Uploaded as zero with every plan.
   uint32_t queue[4][NSGC_QCLASSES * NSGC_QSTRIDE];

@@ -1,6 +1,8 @@
 // Host planner (see nsgc_plan.h for the tiers and phases it lays out).
 #include "nsgc_planner.hpp"
 
+#include "nsgc_large.hpp"
+
 #include <algorithm>
 #include <cstring>
 
@@ -29,6 +31,7 @@ void default_tune(nsgc_tune* t) {
   t->max_rc_buckets_log2 = 10;
   t->max_sweeps_log2 = 24;
   t->combine_probes = 0;
+  t->large_min_log2 = 24;
   for (int k = 0; k <= 32; ++k) {
     t->cls[k].link_target = 2048;
     t->cls[k].row_target = 4096;
@@ -47,6 +50,7 @@ int check_tune(const nsgc_tune& t) {
   if (t.max_rc_buckets_log2 < 0 || t.max_rc_buckets_log2 > 12) return NSGC_ERR_INVALID_ARG;
   if (t.max_sweeps_log2 < 0 || t.max_sweeps_log2 > 24) return NSGC_ERR_INVALID_ARG;
   if (t.combine_probes < 0 || t.combine_probes > 64) return NSGC_ERR_INVALID_ARG;
+  if (t.large_min_log2 < 20 || t.large_min_log2 > 33) return NSGC_ERR_INVALID_ARG;
   for (int k = 0; k <= 32; ++k) {
     const nsgc_tune_class& c = t.cls[k];
     if (c.link_target < 64 || c.row_target < 64 || c.col_target < 64) return NSGC_ERR_INVALID_ARG;
@@ -66,7 +70,12 @@ int validate_offsets(const int64_t* offsets, int64_t num_windows) {
 }
 
 int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune,
-              HostPlan* p) {
+              HostPlan* p, bool entity, bool allow_large) {
+  p->large.clear();
+  p->large_max = 0;
+  p->entity = entity;
+  p->ent_cur.clear();
+  p->ent_end.clear();
   p->small.clear();
   p->win.clear();
   p->prefA.clear();
@@ -99,6 +108,13 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
       p->tier[size_t(w)] = n == 0 ? 0 : 1;
       continue;
     }
+    if (allow_large && !entity && tune.large_min_log2 < 33 &&
+        n >= (uint64_t(1) << tune.large_min_log2)) {
+      p->large.push_back({offsets[w], n, uint32_t(w)});
+      p->large_max = std::max(p->large_max, n);
+      p->tier[size_t(w)] = 3;
+      continue;
+    }
     p->tier[size_t(w)] = 2;
     int cls = 0;
     while (cls < 32 && (uint64_t(1) << (cls + 1)) <= n) ++cls;
@@ -112,6 +128,7 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
     d.logB = uint8_t(std::min(ceil_log2((n + uint64_t(tc.link_target) - 1) / uint64_t(tc.link_target)), capB));
     d.logR = uint8_t(std::min(ceil_log2((n + uint64_t(tc.row_target) - 1) / uint64_t(tc.row_target)), capRC));
     d.logC = uint8_t(std::min(ceil_log2((n + uint64_t(tc.col_target) - 1) / uint64_t(tc.col_target)), capRC));
+    if (entity) d.logR = d.logC = std::max(d.logR, d.logC);   // merged phase-C items
     // one wavefront per link bucket when the window's buckets fit its tables
     if (tc.wave_target > 0 && (1u << d.logR) <= NSGC_WAVE_MAX_RC && (1u << d.logC) <= NSGC_WAVE_MAX_RC) {
       const int lw = ceil_log2((n + uint64_t(tc.wave_target) - 1) / uint64_t(tc.wave_target));
@@ -170,16 +187,23 @@ WsLayout HostPlan::layout() const {
   L.order = o;     o = align_up(o + size_t(itemsC) * 4, 256);
   L.partB = o;     o = align_up(o + size_t(itemsB) * 16, 256);
   L.partC = o;     o = align_up(o + size_t(itemsC) * 16, 256);
+  if (entity) {
+    L.partU = o;   o = align_up(o + size_t(itemsC) * 4, 256);
+    L.stats = o;   o = align_up(o + tier.size() * 72, 256);
+  }
+  if (!large.empty()) {   // shared by the large windows, one after another
+    L.large = o;   o = align_up(o + large_window_bytes(large_max), 256);
+  }
   L.total = std::max<size_t>(o, 256);
   return L;
 }
 
 namespace {
 struct PlanOffsets {
-  size_t small, win, prefA, prefB, prefC, itemwinB, itemwinC, mapBb, mapBw, total;
+  size_t small, win, prefA, prefB, prefC, itemwinB, itemwinC, mapBb, mapBw, entcur, entend, total;
 };
 PlanOffsets plan_offsets(size_t ns, size_t nm, size_t nb, size_t nc, size_t nbb = 0,
-                         size_t nbw = 0) {
+                         size_t nbw = 0, size_t nent = 0) {
   PlanOffsets o;
   size_t x = align_up(sizeof(nsgc_dev_plan), 64);
   o.small = x; x = align_up(x + ns * sizeof(nsgc_small_desc), 64);
@@ -191,6 +215,8 @@ PlanOffsets plan_offsets(size_t ns, size_t nm, size_t nb, size_t nc, size_t nbb 
   o.itemwinC = x; x = align_up(x + nc * 4, 64);
   o.mapBb = x; x = align_up(x + nbb * 4, 64);
   o.mapBw = x; x = align_up(x + nbw * 4, 64);
+  o.entcur = x; x = align_up(x + nent * 8, 64);
+  o.entend = x; x = align_up(x + nent * 8, 64);
   o.total = x;
   return o;
 }
@@ -198,7 +224,7 @@ PlanOffsets plan_offsets(size_t ns, size_t nm, size_t nb, size_t nc, size_t nbb 
 
 size_t HostPlan::plan_bytes() const {
   return plan_offsets(small.size(), win.size(), itemwinB.size(), itemwinC.size(), mapBb.size(),
-                      mapBw.size()).total;
+                      mapBw.size(), ent_cur.size()).total;
 }
 
 size_t plan_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune& t) {
@@ -230,7 +256,7 @@ size_t plan_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune& t) 
 void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const uint32_t* src,
                          const uint32_t* dst, void* out) const {
   const PlanOffsets o = plan_offsets(small.size(), win.size(), itemwinB.size(), itemwinC.size(),
-                                     mapBb.size(), mapBw.size());
+                                     mapBb.size(), mapBw.size(), ent_cur.size());
   const WsLayout L = layout();
   char* base = static_cast<char*>(buf);
   std::memset(base, 0, align_up(sizeof(nsgc_dev_plan), 64));
@@ -270,7 +296,19 @@ void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const ui
   h.small_slots_log2 = small_slots_log2;
   h.max_sweeps_log2 = max_sweeps_log2;
   h.combine_probes = combine_probes;
-  h.order_items = itemsC <= NSGC_ORDER_MAX ? 1u : 0u;
+  h.order_items = itemsC <= NSGC_ORDER_MAX && !entity ? 1u : 0u;
+  if (entity) {
+    // the statistics go to the workspace; the entity counts to the caller
+    h.out = reinterpret_cast<unsigned long long*>(dev_ws + L.stats);
+    h.entity = 1;
+    h.partU = reinterpret_cast<uint32_t*>(dev_ws + L.partU);
+    h.ent_links = static_cast<long long*>(ent_links);
+    h.ent_src = static_cast<long long*>(ent_src);
+    h.ent_dst = static_cast<long long*>(ent_dst);
+    h.ent_counts = static_cast<long long*>(ent_counts);
+    h.ent_cur = reinterpret_cast<unsigned long long*>(dev_plan + o.entcur);
+    h.ent_end = reinterpret_cast<const unsigned long long*>(dev_plan + o.entend);
+  }
   std::memcpy(base, &h, sizeof h);
   if (!small.empty()) std::memcpy(base + o.small, small.data(), small.size() * sizeof(nsgc_small_desc));
   if (!win.empty()) std::memcpy(base + o.win, win.data(), win.size() * sizeof(nsgc_win_desc));
@@ -281,6 +319,8 @@ void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const ui
   if (!itemwinC.empty()) std::memcpy(base + o.itemwinC, itemwinC.data(), itemwinC.size() * 4);
   if (!mapBb.empty()) std::memcpy(base + o.mapBb, mapBb.data(), mapBb.size() * 4);
   if (!mapBw.empty()) std::memcpy(base + o.mapBw, mapBw.data(), mapBw.size() * 4);
+  if (!ent_cur.empty()) std::memcpy(base + o.entcur, ent_cur.data(), ent_cur.size() * 8);
+  if (!ent_end.empty()) std::memcpy(base + o.entend, ent_end.data(), ent_end.size() * 8);
 }
 
 }  // namespace nsgc

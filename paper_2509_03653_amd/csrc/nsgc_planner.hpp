@@ -16,12 +16,21 @@ namespace nsgc {
 // Workspace regions of one batch, as byte offsets from the workspace base.
 struct WsLayout {
   size_t keys = 0, emit_row = 0, emit_col = 0, tilemeta = 0, lbmeta = 0, rcsize = 0, order = 0,
-         partB = 0, partC = 0;
+         partB = 0, partC = 0, partU = 0, stats = 0, large = 0;
   size_t total = 0;
+};
+
+// A window of the large-window tier (computed by sorting, nsgc_large.hpp).
+struct LargeWindow {
+  int64_t in_begin;
+  uint64_t n;
+  uint32_t out_index;
 };
 
 struct HostPlan {
   std::vector<nsgc_small_desc> small;
+  std::vector<LargeWindow> large;
+  uint64_t large_max = 0;      // packets of the largest large window
   std::vector<nsgc_win_desc> win;
   std::vector<uint32_t> prefA, prefB, prefC;
   std::vector<uint32_t> itemwinB, itemwinC;   // window of each phase-B / phase-C item
@@ -34,7 +43,15 @@ struct HostPlan {
   uint32_t tile_log2 = 14, link_slots_log2 = 12, rc_slots_log2 = 12, small_slots_log2 = 11;
   uint32_t max_sweeps_log2 = 24;
   uint32_t combine_probes = 0;
-  std::vector<int32_t> tier;   // per window: 0 empty, 1 small, 2 partitioned
+  std::vector<int32_t> tier;   // per window: 0 empty, 1 small, 2 partitioned, 3 large
+  // Entity outputs (make_plan with entity = true): per window and list the
+  // first and the end row, and the caller's device arrays.
+  bool entity = false;
+  std::vector<uint64_t> ent_cur, ent_end;   // [windows][3]
+  void* ent_links = nullptr;
+  void* ent_src = nullptr;
+  void* ent_dst = nullptr;
+  void* ent_counts = nullptr;
 
   WsLayout layout() const;
   size_t plan_bytes() const;
@@ -50,7 +67,7 @@ int validate_offsets(const int64_t* offsets, int64_t num_windows);
 
 // Builds the plan.  Returns NSGC_OK or NSGC_ERR_* (offsets must be valid).
 int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune,
-              HostPlan* plan);
+              HostPlan* plan, bool entity = false, bool allow_large = true);
 
 void default_tune(nsgc_tune* t);
 int check_tune(const nsgc_tune& t);

@@ -210,6 +210,33 @@ def test_wavefront_and_workgroup_windows_in_one_batch():
     check(src, dst, off, "wavefront and workgroup windows", forms=("batched", "plain", "graph"))
 
 
+def test_addresses_hashed_to_the_empty_marker():
+    # the source and destination whose hashed forms equal the tables' empty
+    # marker (and their link, whose key is the 64-bit marker) are counted
+    # outside the tables, in every tier and phase-B kernel
+    from hashed_addresses import DESTINATION_MARKER, SOURCE_MARKER
+    rng = np.random.default_rng(17)
+    sizes = [7, 900, 5000, 300000, 1500, 70000]
+    off = synth.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    pool = np.array([SOURCE_MARKER, DESTINATION_MARKER, 0, 0xFFFFFFFF, 5, 6], np.uint32)
+    src = pool[rng.integers(0, pool.size, n)]
+    dst = pool[rng.integers(0, pool.size, n)]
+    src[::3] = SOURCE_MARKER
+    dst[::3] = DESTINATION_MARKER
+    wide = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    src[1::4] = wide[1::4]                   # enough distinct links for the larger tiers
+    for form in ("batched", "plain", "graph"):
+        check(src, dst, off, "marker addresses", forms=(form,))
+    for name, extra in (("workgroup", dict(cls=[[2048, 4096, 4096, 0]] * 33)),
+                        ("sweeps", dict(link_slots_log2=10, rc_slots_log2=10,
+                                        cls=[[65536, 65536, 65536, 2048]] * 33))):
+        base = nsgc.default_tune().to_dict()
+        base.update(extra)
+        nsgc.set_tune(nsgc.Tune.from_dict(base))
+        check(src, dst, off, f"marker addresses, {name}")
+
+
 def test_repeated_runs_identical_and_nonzero_first_offset():
     wl = synth.uneven_batch(seed=5, num_windows=30, lo_log2=8, hi_log2=16)
     src, dst = wl.generate()

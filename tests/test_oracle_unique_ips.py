@@ -100,7 +100,8 @@ def test_empty_windows_and_offsets():
 
 
 MUTANTS = {
-    "sources_only": ("    ips.insert(dst[i]);\n", ""),
+    "sources_only": ("  for (int64_t i = begin; i < end; ++i) {\n    ips.insert(src[i]);\n    ips.insert(dst[i]);\n  }",
+                     "  for (int64_t i = begin; i < end; ++i) {\n    ips.insert(src[i]);\n  }"),
     "common_counted_twice": ("  std::set<uint32_t> ips;\n  for (int64_t i = begin; i < end; ++i) {\n    ips.insert(src[i]);\n    ips.insert(dst[i]);\n  }\n  return static_cast<uint64_t>(ips.size());",
                              "  std::set<uint32_t> a, b;\n  for (int64_t i = begin; i < end; ++i) {\n    a.insert(src[i]);\n    b.insert(dst[i]);\n  }\n  return static_cast<uint64_t>(a.size() + b.size());"),
     "last_packet_lost": ("  std::set<uint32_t> ips;\n  for (int64_t i = begin; i < end; ++i) {",
