@@ -43,8 +43,6 @@ HBM_PEAK_GBS = 8000.0                     # MI355X HBM3E, 8 TB/s
 COPIES = 8
 CALIB_BYTES = 1 << 30                     # calibration copy: 1 GiB read + 1 GiB written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_zipf_64x2^17.json")
-KERNEL_NAMES = {"small": "k_small", "partition": "k_partition", "links": "k_links",
-                "rowcol": "k_rowcol"}
 # the launches each timed phase covers (the link phase is one of two kernels,
 # the row/column phase includes the ordering and the per-window combine)
 PHASE_KERNELS = {"small": ["k_small"], "partition": ["k_partition"],
@@ -278,7 +276,10 @@ def cpu_baseline_full(src, dst, offsets, budget_s: float):
 
 
 def summarize_pmc(fetch_dir, write_dir):
-    """Scale FETCH_SIZE / WRITE_SIZE per dispatch by the calibration copy."""
+    """Scale FETCH_SIZE / WRITE_SIZE per dispatch by the calibration copy and
+    sum them per timed phase (the kernels of PHASE_KERNELS)."""
+    import re
+
     def rows(d):
         files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
         if not files:
@@ -295,10 +296,12 @@ def summarize_pmc(fetch_dir, write_dir):
             if r.get("Counter_Name") != counter:
                 continue
             name = r["Kernel_Name"]
-            key = next((k for k, v in KERNEL_NAMES.items() if v in name), None)
-            if key is None and ("copy" in name.lower() or "elementwise" in name.lower()):
+            m = re.search(r"nsgc::(k_\w+)", name)
+            if m:
+                key = m.group(1)
+            elif "copy" in name.lower() or "elementwise" in name.lower():
                 key = "copies"
-            if key is None:
+            else:
                 continue
             acc.setdefault(key, {})
             disp = r.get("Dispatch_Id", r.get("Correlation_Id"))
@@ -315,13 +318,19 @@ def summarize_pmc(fetch_dir, write_dir):
     f_scale = (CALIB_BYTES / 1024.0) / cal_f if cal_f else None
     w_scale = (CALIB_BYTES / 1024.0) / cal_w if cal_w else None
     result = {"kernel_source": kernel_source_hash(), "calibration_bytes": CALIB_BYTES,
-              "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
-    for k in KERNEL_NAMES:
-        if k in fetch or k in write:
-            fb = fetch.get(k, 0.0) * 1024.0 * (f_scale or 1.0)
-            wb = write.get(k, 0.0) * 1024.0 * (w_scale or 1.0)
-            result["kernels"][k] = {"fetch_kib_raw": fetch.get(k), "write_kib_raw": write.get(k),
-                                    "hbm_bytes": fb + wb}
+              "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}, "phases": {}}
+    for k in sorted(set(fetch) | set(write)):
+        if k == "calibration_copy":
+            continue
+        fb = fetch.get(k, 0.0) * 1024.0 * (f_scale or 1.0)
+        wb = write.get(k, 0.0) * 1024.0 * (w_scale or 1.0)
+        result["kernels"][k] = {"fetch_kib_raw": fetch.get(k), "write_kib_raw": write.get(k),
+                                "hbm_bytes": fb + wb}
+    for ph, ks in PHASE_KERNELS.items():
+        got = [result["kernels"][k]["hbm_bytes"] for k in ks if k in result["kernels"]]
+        if got:
+            result["phases"][ph] = {"hbm_bytes": float(sum(got)),
+                                    "kernels": [k for k in ks if k in result["kernels"]]}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(result, fh, indent=1)
@@ -492,8 +501,8 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_source") == kernel_source_hash() and dominant in tr.get("kernels", {}):
-            traffic = tr["kernels"][dominant]["hbm_bytes"]
+        if tr.get("kernel_source") == kernel_source_hash() and dominant in tr.get("phases", {}):
+            traffic = tr["phases"][dominant]["hbm_bytes"]
 
     serving = None
     if args.serving_windows > 0 and args.workload == "zipf_batch":

@@ -131,14 +131,21 @@ __device__ __forceinline__ u64 link_key(uint32_t s, uint32_t d, bool same = fals
   return (u64(row_hash(s)) << 32) | (same ? row_hash(d) : col_hash(d));
 }
 
-// Position bits of a hashed link key: the link bucket is the top bits, the
-// overflow sweeps take the bits that follow, and the low 32 bits pick the
-// LDS table slot.  Both halves of the key are already mixed, so crossing them
-// with rotations is enough to make every bit depend on source and
-// destination (a star or a reverse star still spreads over all buckets).
+// Position bits of a hashed link key (r, c): the link bucket is the top bits,
+// the overflow sweeps take the bits that follow, and the low bits pick the
+// LDS table slot.  hi = r ^ rotl(c, 13), lo = c ^ hi, a bijection of (r, c).
+// Both halves of the key are already mixed, so the rotation is enough to make
+// every bit depend on source and destination, and the bits are placed so that
+// the slot stays uniform inside one bucket for the links of one source and for
+// those of one destination: with the top j bits of hi fixed, a fixed c fixes
+// r's top j bits while slot bit i < 13 still gets r's bit i (j <= 19), and a
+// fixed r fixes c's bits 19 - j .. 18 while slot bit i still gets c's bit
+// i + 19.  (A slot taken from bits of r that the bucket fixes would put all
+// the links of a popular destination in a few probe chains.)
 __device__ __forceinline__ u64 link_pos(u64 k) {
   const uint32_t r = uint32_t(k >> 32), c = uint32_t(k);
-  return (u64(r ^ rotl32(c, 13)) << 32) | (c ^ rotl32(r, 7));
+  const uint32_t hi = r ^ rotl32(c, 13);
+  return (u64(hi) << 32) | (c ^ hi);
 }
 
 // top k bits (k may be 0)

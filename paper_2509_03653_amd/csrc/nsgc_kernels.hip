@@ -437,12 +437,19 @@ __global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restric
         ok[4 * k + 0] = ok[4 * k + 1] = ok[4 * k + 2] = ok[4 * k + 3] = true;
       }
     } else {
+      // unaligned or partial tile: element loads, all issued before any is
+      // used (a lane past the end loads the tile's first packet and is masked)
+      uint32_t sv[PER], dv[PER];
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
         const uint32_t idx = k * NT + threadIdx.x;
         ok[k] = idx < len;
-        key[k] = ok[k] ? link_key(src[idx], dst[idx], same) : 0ull;
+        const uint32_t at = ok[k] ? idx : 0u;
+        sv[k] = src[at];
+        dv[k] = dst[at];
       }
+#pragma unroll
+      for (int k = 0; k < PER; ++k) key[k] = link_key(sv[k], dv[k], same);
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -1261,9 +1268,16 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P) {
     const NSGC_GLOBAL uint32_t* tm0 = gptr(P->tilemeta) + W.tilemeta + u64(b) * nt;
     NSGC_GLOBAL uint32_t* rec = gptr(P->lbmeta) + W.lbmeta;
 
-    // Emission base of bucket b: the sum of its starts over the tiles.
-    uint32_t below = 0;
-    for (uint32_t t = lane; t < nt; t += 64) below += tm0[t];
+    // The bucket's starts and ends in the first 64 tiles (lane = tile), loaded
+    // once for every build of the item; the emission base of bucket b is the
+    // sum of its starts over all tiles.
+    uint32_t a0 = 0, c0 = 0;
+    if (lane < nt) {
+      a0 = tm0[lane];
+      c0 = tm0[lane + nt];
+    }
+    uint32_t below = a0;
+    for (uint32_t t = 64 + lane; t < nt; t += 64) below += tm0[t];
     below = uniform(wave_sum(below));
 
     uint32_t n = 0;        // occupied slots (uniform)
@@ -1279,7 +1293,7 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P) {
         u64 mb = 0;
         uint32_t len = 0;
         if (t < nt) {
-          const uint32_t a = tm0[t], c = tm0[t + nt];
+          const uint32_t a = g0 == 0 ? a0 : tm0[t], c = g0 == 0 ? c0 : tm0[t + nt];
           mb = u64(t) * T + a;
           len = c - a;
         }

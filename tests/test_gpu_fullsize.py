@@ -4,9 +4,10 @@ configuration (the captured-graph batched form).
   * 1 window of 2^17, uniform over 4096 addresses: every statistic vs the oracle.
   * 64 windows of 2^17 (the benchmark batch): every window vs the oracle.
   * 128 windows of 2^23 with a super-source and a super-destination (2^30
-    packets): sampled windows vs the oracle, exact invariants on every window.
-  * 4096 windows log-uniform in [2^10, 2^23] (~3.8e9 packets): sampled windows
-    vs the oracle, exact invariants on every window.
+    packets): every window vs the oracle (one window per host thread).
+  * 4096 windows log-uniform in [2^10, 2^23] (~3.8e9 packets): every window
+    of at least 2^22 packets and a random 5% of the others vs the oracle,
+    exact invariants on every window.
 
 The invariants hold for any exact result and are checked on all windows:
 stat0 = n; max(stat3, stat6) <= stat1 <= min(n, stat3 * stat6);
@@ -72,7 +73,7 @@ def sampled_oracle(src, dst, off, windows):
     s = np.concatenate([src[a:b] for a, b in parts])
     d = np.concatenate([dst[a:b] for a, b in parts])
     o = synth.offsets_from_sizes([b - a for a, b in parts])
-    return oracle.window_stats(s, d, o, threads=len(parts))
+    return oracle.window_stats(s, d, o, threads=min(len(parts), _host_threads()))
 
 
 def test_uniform_single_window_full():
@@ -94,27 +95,39 @@ def test_benchmark_batch_full():
     assert_same(got, want, "64 x 2^17")
 
 
-def test_skewed_2e30_packets_sampled():
+def _host_threads():
+    import os
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:  # pragma: no cover
+        return 8
+
+
+def test_skewed_2e30_packets_every_window():
     wl = synth.skewed_large(seed=1)
     say("[cpu] generating 128 x 2^23 packets")
     src, dst = wl.generate()
     got = graph_stats(src, dst, wl.offsets)
     invariants(got, np.diff(wl.offsets))
-    sample = [0, 1, 63, 127]
-    assert_same(got[sample], sampled_oracle(src, dst, wl.offsets, sample), "skewed sample")
+    say("[cpu] oracle on all 128 windows")
+    want = oracle.window_stats(src, dst, wl.offsets, threads=_host_threads())
+    assert_same(got, want, "skewed 128 x 2^23")
     # the super-source (10% of packets) dominates the row maxima
     assert np.all(got[:, 4] >= (1 << 23) // 20)
 
 
-def test_uneven_4096_windows_sampled():
+def test_uneven_4096_windows_large_ones_and_a_sample():
     wl = synth.uneven_batch(seed=1)
     say(f"[cpu] generating {wl.num_packets} packets in 4096 windows")
     src, dst = wl.generate()
     sizes = np.diff(wl.offsets)
     got = graph_stats(src, dst, wl.offsets)
     invariants(got, sizes)
-    order = np.argsort(sizes)
     rng = np.random.default_rng(7)
-    sample = sorted(set(order[:3].tolist() + order[-2:].tolist() +
-                        rng.choice(len(sizes), 6, replace=False).tolist()))
-    assert_same(got[sample], sampled_oracle(src, dst, wl.offsets, sample), "uneven sample")
+    big = np.flatnonzero(sizes >= (1 << 22))
+    small = np.flatnonzero(sizes < (1 << 22))
+    sample = sorted(set(big.tolist()) | set(rng.choice(small, len(small) // 20, replace=False).tolist())
+                    | {int(np.argmin(sizes))})
+    say(f"[cpu] oracle on {len(sample)} windows ({len(big)} of at least 2^22 packets)")
+    want = sampled_oracle(src, dst, wl.offsets, sample)
+    assert_same(got[sample], want, "uneven: large windows and a 5% sample")
