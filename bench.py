@@ -42,7 +42,26 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0                     # MI355X HBM3E, 8 TB/s
 COPIES = 8
 CALIB_BYTES = 1 << 30                     # calibration copy: 1 GiB read + 1 GiB written
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_zipf_64x2^17.json")
+# measured HBM traffic per workload (written by --summarize-pmc), keyed by kernel sources
+TRAFFIC_NAMES = {"zipf_batch": "zipf_64x2^17", "uniform_single": "uniform_1x2^17",
+                 "skewed_large": "skewed_128x2^23", "uneven_batch": "uneven_4096"}
+
+
+def traffic_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{TRAFFIC_NAMES[workload]}.json")
+
+
+def measured_traffic(workload: str, phase: str):
+    """HBM bytes per launch of `phase` from the stored counters, or None when
+    none were taken or the kernel sources have changed since."""
+    f = traffic_file(workload)
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        tr = json.load(fh)
+    if tr.get("kernel_source") != kernel_source_hash() or phase not in tr.get("phases", {}):
+        return None
+    return tr["phases"][phase]["hbm_bytes"]
 # the launches each timed phase covers (the link phase is one of two kernels,
 # the row/column phase includes the ordering and the per-window combine)
 PHASE_KERNELS = {"small": ["k_small"], "partition": ["k_partition"],
@@ -72,6 +91,22 @@ WORKLOAD_TEXT = {
     "uneven_batch": "4096 windows, sizes log-uniform in [2^10, 2^23], Zipf(1.1) over 2^22 "
                     "addresses",
 }
+
+
+def tune_with(nsgc, spec: str):
+    """The default tuning with `key=value` overrides (comma-separated)."""
+    t = nsgc.default_tune()
+    per_class = ("link_target", "row_target", "col_target", "wave_target")
+    for kv in filter(None, spec.split(",")):
+        k, v = kv.split("=")
+        if k in per_class:
+            for c in t.cls:
+                setattr(c, k, int(v))
+        elif k in nsgc.Tune.SCALARS:
+            setattr(t, k, int(v))
+        else:
+            raise SystemExit(f"unknown tuning knob {k!r}")
+    return t
 
 
 def make_inputs(args):
@@ -225,7 +260,8 @@ def large_leg(nsgc, torch, seed, steps=5):
             "step_roofline_frac": alg / (ms_g * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "roofline": {"bound": "hbm", "phase": dom, "kernels": PHASE_KERNELS[dom],
                          "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": ach / HBM_PEAK_GBS}}
+                         "frac": ach / HBM_PEAK_GBS,
+                         "traffic": measured_traffic("skewed_large", dom)}}
 
 
 def cpu_baseline(src, dst, offsets, budget_s: float):
@@ -275,24 +311,42 @@ def cpu_baseline_full(src, dst, offsets, budget_s: float):
     return r
 
 
-def summarize_pmc(fetch_dir, write_dir):
+def counter_rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    out = []
+    for f in files:
+        with open(f) as fh:
+            out.extend(csv.DictReader(fh))
+    return out
+
+
+def summarize_counters(d):
+    """Mean per dispatch of every counter in a rocprofv3 --pmc run, per library
+    kernel, as one JSON object {kernel: {counter: value}}."""
+    import re
+    acc = {}
+    for r in counter_rows(d):
+        m = re.search(r"nsgc::(k_\w+)", r["Kernel_Name"])
+        if not m:
+            continue
+        disp = r.get("Dispatch_Id", r.get("Correlation_Id"))
+        k = acc.setdefault(m.group(1), {}).setdefault(r["Counter_Name"], {})
+        k[disp] = k.get(disp, 0.0) + float(r["Counter_Value"])
+    res = {kern: {c: float(np.mean(list(v.values()))) for c, v in sorted(cs.items())}
+           for kern, cs in sorted(acc.items())}
+    print(json.dumps(res, indent=1))
+
+
+def summarize_pmc(fetch_dir, write_dir, workload="zipf_batch"):
     """Scale FETCH_SIZE / WRITE_SIZE per dispatch by the calibration copy and
     sum them per timed phase (the kernels of PHASE_KERNELS)."""
     import re
 
-    def rows(d):
-        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-        if not files:
-            raise SystemExit(f"no counter_collection.csv under {d}")
-        out = []
-        for f in files:
-            with open(f) as fh:
-                out.extend(csv.DictReader(fh))
-        return out
-
     def per_kernel(d, counter):
         acc = {}
-        for r in rows(d):
+        for r in counter_rows(d):
             if r.get("Counter_Name") != counter:
                 continue
             name = r["Kernel_Name"]
@@ -331,8 +385,10 @@ def summarize_pmc(fetch_dir, write_dir):
         if got:
             result["phases"][ph] = {"hbm_bytes": float(sum(got)),
                                     "kernels": [k for k in ks if k in result["kernels"]]}
-    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
-    with open(TRAFFIC_FILE, "w") as fh:
+    result["workload"] = WORKLOAD_TEXT[workload]
+    path = traffic_file(workload)
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
         json.dump(result, fh, indent=1)
     print(json.dumps(result))
 
@@ -418,10 +474,18 @@ def main():
     ap.add_argument("--no-extra-legs", action="store_true",
                     help="skip the single-window latency and the 2^30-packet legs")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-counters", metavar="PMC_DIR",
+                    help="print the per-kernel mean of every counter of a rocprofv3 --pmc run")
+    ap.add_argument("--tune", default="",
+                    help="tuning overrides, e.g. 'max_link_buckets_log2=11,wave_target=0' "
+                         "(per-class targets apply to every size class)")
     args = ap.parse_args()
 
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc)
+        summarize_pmc(*args.summarize_pmc, workload=args.workload)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the statistics of independent windows need no "
@@ -434,6 +498,8 @@ def main():
     import paper_2509_03653_amd as nsgc
 
     torch.cuda.set_device(0)
+    if args.tune:
+        nsgc.set_tune(tune_with(nsgc, args.tune))
     wl, src, dst = make_inputs(args)
     off = wl.offsets
     P, W = wl.num_packets, wl.num_windows
@@ -441,7 +507,12 @@ def main():
     ss, dd = to_device_copies(src, dst, copies)
     stream = torch.cuda.current_stream()
     out = torch.empty((W, 9), dtype=torch.int64, device="cuda")
-    graph = nsgc.Graph(P, W)
+    tuned = None
+    if args.autotune:   # before the timed graph: each trial holds a workspace of its own
+        from paper_2509_03653_amd import autotune
+        tuned = autotune.tune_for(ss[0], dd[0], off, budget_s=120.0)
+        nsgc.release()
+    graph = nsgc.Graph(P, W)          # a graph keeps the tuning it was created with
 
     if args.profile_steps:
         for i in range(args.profile_steps):
@@ -457,12 +528,6 @@ def main():
         graph.close()
         return
 
-    tuned = None
-    if args.autotune:
-        from paper_2509_03653_amd import autotune
-        tuned = autotune.tune_for(ss[0], dd[0], off, budget_s=120.0)
-        graph.close()
-        graph = nsgc.Graph(P, W)          # a graph keeps the tuning it was created with
 
     # parity gate on sampled windows before timing
     graph.launch(ss[0], dd[0], off, out=out, stream=stream)
@@ -497,12 +562,7 @@ def main():
     alg = algorithmic_bytes(P, W)
     achieved = alg / (phase_ms[dominant] * 1e-3) / 1e9
 
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        if tr.get("kernel_source") == kernel_source_hash() and dominant in tr.get("phases", {}):
-            traffic = tr["phases"][dominant]["hbm_bytes"]
+    traffic = None if args.tune or args.autotune else measured_traffic(args.workload, dominant)
 
     serving = None
     if args.serving_windows > 0 and args.workload == "zipf_batch":
@@ -536,7 +596,8 @@ def main():
         "data": f"synthetic (seeded traffic; inputs resident in HBM, {copies} rotating "
                 f"cop{'ies' if copies > 1 else 'y'})",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
-                   "windows": W, "packets": P, "seed": args.seed, "form": "batched, graph"},
+                   "windows": W, "packets": P, "seed": args.seed, "form": "batched, graph",
+                   "tuning": "autotuned" if args.autotune else (args.tune or "default")},
         "batched_direct_packets_per_s": P / (ms_direct * 1e-3),
         "plain_packets_per_s": P / (ms_plain * 1e-3),
         "plain_ms_per_step": ms_plain,

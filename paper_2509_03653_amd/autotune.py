@@ -39,10 +39,11 @@ SPACE = (
     ("link_scale", (0.5, 1.0, 2.0)),
     ("max_link_buckets_log2", (10, 11, 12)),
     ("rc_scale", (0.5, 1.0, 2.0)),
+    ("wave_target", (0, 128, 256, 512)),
     ("combine_probes", (0, 64)),
 )
 
-CACHE_VERSION = 2
+CACHE_VERSION = 3
 
 
 def size_classes(offsets) -> np.ndarray:
@@ -99,6 +100,9 @@ def apply_point(base: dict, point: dict, classes) -> dict:
             for c in classes:
                 d["cls"][c][1] = max(64, int(d["cls"][c][1] * v))
                 d["cls"][c][2] = max(64, int(d["cls"][c][2] * v))
+        elif k == "wave_target":
+            for c in classes:
+                d["cls"][c][3] = int(v)
         else:
             d[k] = v
     return d
@@ -108,6 +112,9 @@ def start_point(base: dict) -> dict:
     p = {k: base[k] for k, _ in SPACE if k in base}
     p["link_scale"] = 1.0
     p["rc_scale"] = 1.0
+    waves = {row[3] for row in base["cls"] if len(row) > 3}
+    if len(waves) == 1:
+        p["wave_target"] = waves.pop()
     return p
 
 

@@ -657,8 +657,8 @@ __device__ __forceinline__ void gather_by_wave(uint32_t nseg, SegFn seg, BatchFn
 // If an insert gives up (more distinct keys than the table holds), the bucket
 // is split into 2^s sweeps by further hash bits and redone; the sweeps
 // partition the keys, so the result is unchanged.  With sweeps, every sweep
-// emits its own links uncombined (links = 1), counted in a first pass and
-// written in a second.
+// emits its own links uncombined (links = 1) right after its build, into
+// row and column segments sized by the bucket's packets (see the sweep loop).
 // ---------------------------------------------------------------------------
 
 size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_rc_buckets) {
@@ -776,8 +776,10 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
       __syncthreads();
     };
 
-    // Link table of sweep `sw` of 2^logS.
-    auto build = [&](uint32_t logS, uint32_t sw) {
+    // Link table of sweep `sw` of 2^logS.  With `cap`, every packet of the
+    // bucket (of any sweep) is also counted in histR / histC by its row and
+    // column bucket.
+    auto build = [&](uint32_t logS, uint32_t sw, bool cap) {
       if (threadIdx.x < 2) misc[threadIdx.x] = 0;
       __syncthreads();
       gather_by_wave<LINK_MAXU>(nt, seg, [&](const auto& pos, const auto& okin) {
@@ -789,6 +791,15 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
         for (int u = 0; u < U; ++u) {   // unconditional load (position 0 exists), then mask
           const u64 kk = keys[okin[u] ? pos[u] : 0ull];
           key[u] = okin[u] ? kk : 0ull;
+        }
+        if (cap) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (okin[u]) {
+              lds_add(&histR[top32(uint32_t(key[u] >> 32), W.logR)], 1);
+              lds_add(&histC[top32(uint32_t(key[u]), W.logC)], 1);
+            }
+          }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1058,6 +1069,15 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 
     // Attempt with 2^logS sweeps; any insert that gives up restarts the whole
     // bucket with twice the sweeps (the emission is rewritten from scratch).
+    // A single sweep counts its links per row and column bucket and emits
+    // them packed.  With sweeps, the first sweep's gather counts the bucket's
+    // packets per row and column bucket instead: each row (column) bucket's
+    // segment gets one slot per packet, the most entries it can receive, so
+    // every sweep emits right after its build, and the slots left over hold
+    // empty entries (packet count 0), which phase C skips.  The entity
+    // outputs list each link once, so there the sweeps first all build and
+    // count (pass 0) and then build again to emit (pass 1): a restart never
+    // follows a partial emission.
     uint32_t links = 0, sum = 0, mx = 0;
     bool abandoned = false;
     for (uint32_t logS = 0;; ++logS) {
@@ -1066,10 +1086,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
       for (uint32_t i = threadIdx.x; i < R; i += NSGC_BLOCK) histR[i] = 0;
       for (uint32_t i = threadIdx.x; i < C; i += NSGC_BLOCK) histC[i] = 0;
       bool failed = false;
-      // pass 0: statistics and link counts (a single sweep also emits);
-      // pass 1 (sweeps only): emission at the counted positions.  One call
-      // site of each step keeps the kernel's code small.
-      const uint32_t passes = logS ? 2u : 1u;
+      const uint32_t passes = logS && P->ent_links ? 2u : 1u;
 #pragma nounroll
       for (uint32_t pass = 0; pass < passes && !failed; ++pass) {
         if (pass == 1) {
@@ -1078,7 +1095,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
         }
 #pragma nounroll
         for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
-          build(logS, sw);
+          build(logS, sw, logS > 0 && sw == 0 && passes == 1);
           if (misc[0]) { failed = true; reset(); break; }
           if (pass == 1) {
             emit();
@@ -1123,10 +1140,26 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
             reset();
             combine_emit(true, lkey, lcnt, n, spc);
             combine_emit(false, lkey, lcnt, n, spc);
-          } else {
+          } else if (passes == 2) {
             count();
             __syncthreads();
             reset();
+          } else {
+            if (sw == 0) {   // the slot counts become the segment starts and cursors
+              publish();
+              __syncthreads();
+              const uint32_t nb = histR[R];   // the bucket's packets: its whole region
+              NSGC_GLOBAL u64* er = gptr(P->emit_row) + W.ws + misc[4];
+              NSGC_GLOBAL u64* ec = gptr(P->emit_col) + W.ws + misc[4];
+              for (uint32_t i = threadIdx.x; i < nb; i += NSGC_BLOCK) {
+                er[i] = 0ull;
+                ec[i] = 0ull;
+              }
+              __threadfence_block();   // the empty entries land before any emission
+              __syncthreads();
+            }
+            emit();
+            if (threadIdx.x == 0) misc[5] = 0;   // ordered by the next build's barrier
           }
         }
       }
@@ -1682,7 +1715,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           h[u] = id[u];
-          ok[u] = okin[u] && !(logS && next32(h[u], logK, logS) != sw);
+          // (an entry with no packets is an unused slot of a swept link bucket)
+          ok[u] = okin[u] && pk[u] != 0 && !(logS && next32(h[u], logK, logS) != sw);
           if (ok[u] && id[u] == EMPTY32) {
             lds_add(&misc[2], pk[u]);
             lds_add(&misc[3], ln[u]);
@@ -1848,7 +1882,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol_ent(nsgc_dev_plan* P) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           h[u] = id[u];
-          ok[u] = okin[u] && !(logS && next32(h[u], logK, logS) != sw);
+          // (an entry with no packets is an unused slot of a swept link bucket)
+          ok[u] = okin[u] && pk[u] != 0 && !(logS && next32(h[u], logK, logS) != sw);
           if (ok[u] && id[u] == EMPTY32) {
             lds_add(&spc[0], pk[u]);
             lds_add(&spc[1], ln[u]);

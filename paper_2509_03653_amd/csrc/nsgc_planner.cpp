@@ -27,16 +27,22 @@ void default_tune(nsgc_tune* t) {
   t->link_slots_log2 = 12;
   t->rc_slots_log2 = 12;
   t->blocks_per_cu = 3;
-  t->max_link_buckets_log2 = 10;
+  t->max_link_buckets_log2 = 11;
   t->max_rc_buckets_log2 = 10;
   t->max_sweeps_log2 = 24;
   t->combine_probes = 0;
   t->large_min_log2 = 24;
+  // Per size class (windows of [2^k, 2^(k+1)) packets): below 2^23 packets a
+  // link bucket holds at most as many packets as its LDS table has slots (at
+  // 2^23, twice as many; larger windows repeat links more), a row or column
+  // bucket at most twice as many, so a bucket sweeps only when nearly all its
+  // packets are distinct links (ids).  Windows below 2^19 packets keep the
+  // smaller buckets, which measured faster there.
   for (int k = 0; k <= 32; ++k) {
-    t->cls[k].link_target = 2048;
-    t->cls[k].row_target = 4096;
-    t->cls[k].col_target = 4096;
-    t->cls[k].wave_target = 256;
+    nsgc_tune_class& c = t->cls[k];
+    c.link_target = k < 19 ? 2048 : k < 23 ? 4096 : 8192;
+    c.row_target = c.col_target = k < 19 ? 4096 : 8192;
+    c.wave_target = 256;
   }
 }
 

@@ -137,6 +137,36 @@ def test_plan_tiers_and_cutover():
     assert p["workspace_bytes"] >= 24 * (sum(sizes[3:]))
 
 
+def test_default_buckets_sized_by_their_tables():
+    """Under the default tuning, a link bucket of a partitioned window below
+    2^23 packets holds at most as many packets as its LDS table has slots (at
+    2^23, twice as many), and a row or column bucket at most twice as many:
+    so a bucket needs an overflow sweep only when nearly all its packets are
+    distinct links (ids), however the window's packets are spread.  Wavefront
+    buckets are checked against the wavefront table (2^9 slots)."""
+    t = nsgc.default_tune()
+    nsgc.set_tune(t)
+    sizes = sorted({int(x) for x in np.unique(np.round(2.0 ** np.linspace(
+        np.log2(t.small_max + 1), 23, 400)))} | {(1 << k) + d for k in range(11, 24)
+                                                for d in (-1, 0, 1)} - {1 << 23 | 1})
+    sizes = [n for n in sizes if t.small_max < n <= 1 << 23]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    p = nsgc.plan_inspect(off)
+    assert (p["tier"] == 2).all()
+    link_slots, rc_slots = 1 << t.link_slots_log2, 1 << t.rc_slots_log2
+    for i, n in enumerate(sizes):
+        lb, lr, lc = (int(p[k][i]) for k in ("log2_link_buckets", "log2_row_buckets",
+                                             "log2_col_buckets"))
+        cls = n.bit_length() - 1
+        wave = (t.cls[cls].wave_target > 0 and lr <= 8 and lc <= 8
+                and lb == int(np.ceil(np.log2(-(-n // t.cls[cls].wave_target)))))
+        per_link = -(-n // (1 << lb))
+        room = 512 if wave else link_slots
+        assert per_link <= (room if n < 1 << 23 else 2 * room), (n, lb, wave)
+        assert -(-n // (1 << lr)) <= 2 * rc_slots, (n, lr)
+        assert -(-n // (1 << lc)) <= 2 * rc_slots, (n, lc)
+
+
 def test_plan_rejects_bad_offsets():
     with pytest.raises(nsgc.NsgcError):
         nsgc.plan_inspect(np.array([0, 5, 2], np.int64))

@@ -30,10 +30,12 @@ def test_signature_is_coarse_and_stable():
 
 def test_apply_point_scales_only_present_classes():
     base = nsgc.default_tune().to_dict()
-    d = at.apply_point(base, {"blocks_per_cu": 3, "link_scale": 2.0, "rc_scale": 0.5}, [17])
+    d = at.apply_point(base, {"blocks_per_cu": 3, "link_scale": 2.0, "rc_scale": 0.5,
+                              "wave_target": 0}, [17])
     assert d["blocks_per_cu"] == 3
     assert d["cls"][17][0] == 2 * base["cls"][17][0]
     assert d["cls"][17][1] == base["cls"][17][1] // 2
+    assert d["cls"][17][3] == 0 and base["cls"][17][3] > 0
     assert d["cls"][16] == base["cls"][16]
     nsgc.Tune.from_dict(d)   # a valid tuning structure
 
@@ -54,7 +56,7 @@ def test_search_finds_the_separable_optimum():
     # cost model with a known optimum; coordinate descent must reach it
     opt = {"blocks_per_cu": 3, "link_slots_log2": 11, "rc_slots_log2": 13, "tile_log2": 14,
            "small_max": 512, "link_scale": 2.0, "max_link_buckets_log2": 11, "rc_scale": 0.5,
-           "combine_probes": 64}
+           "wave_target": 128, "combine_probes": 64}
     assert set(opt) == {k for k, _ in at.SPACE}
     calls = []
 

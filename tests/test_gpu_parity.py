@@ -194,10 +194,11 @@ def test_every_tuning_gives_identical_results(name):
 
 
 def test_wavefront_and_workgroup_windows_in_one_batch():
-    # windows up to 2^18 packets take link aggregation one wavefront per bucket,
-    # larger ones one workgroup per bucket; both kernels draw their items from
-    # their own list of the batch's phase-B items
-    sizes = [5000, 300000, 70000, 1 << 19, 1500, 0, 2000, 262144, 262145, 40000]
+    # windows up to 2^19 packets take link aggregation one wavefront per bucket
+    # (under the default tuning), larger ones one workgroup per bucket; both
+    # kernels draw their items from their own list of the batch's phase-B items
+    sizes = [5000, 300000, 70000, 1 << 19, 1500, 0, 2000, 600000, 262145, 40000,
+             (1 << 20) + 3]
     off = synth.offsets_from_sizes(sizes)
     wl = synth.zipf_batch(seed=3, num_windows=1, log2_window=4)
     src, dst = synth.fill(off, 12, wl.src_dist, wl.dst_dist)
