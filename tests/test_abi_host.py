@@ -140,10 +140,12 @@ def test_plan_tiers_and_cutover():
 def test_default_buckets_sized_by_their_tables():
     """Under the default tuning, a link bucket of a partitioned window below
     2^23 packets holds at most as many packets as its LDS table has slots (at
-    2^23, twice as many), and a row or column bucket at most twice as many:
-    so a bucket needs an overflow sweep only when nearly all its packets are
-    distinct links (ids), however the window's packets are spread.  Wavefront
-    buckets are checked against the wavefront table (2^9 slots)."""
+    2^23, twice as many), so it needs an overflow sweep only when nearly all
+    its packets are distinct links, however the window's packets are spread.
+    Row and column buckets hold at most twice as many packets as table slots
+    below 2^19 packets and four times as many above (their ids, sources or
+    destinations, repeat far more than links).  Wavefront buckets are checked
+    against the wavefront table (2^9 slots)."""
     t = nsgc.default_tune()
     nsgc.set_tune(t)
     sizes = sorted({int(x) for x in np.unique(np.round(2.0 ** np.linspace(
@@ -163,8 +165,9 @@ def test_default_buckets_sized_by_their_tables():
         per_link = -(-n // (1 << lb))
         room = 512 if wave else link_slots
         assert per_link <= (room if n < 1 << 23 else 2 * room), (n, lb, wave)
-        assert -(-n // (1 << lr)) <= 2 * rc_slots, (n, lr)
-        assert -(-n // (1 << lc)) <= 2 * rc_slots, (n, lc)
+        rc_room = (2 if n < 1 << 19 else 4) * rc_slots
+        assert -(-n // (1 << lr)) <= rc_room, (n, lr)
+        assert -(-n // (1 << lc)) <= rc_room, (n, lc)
 
 
 def test_plan_rejects_bad_offsets():
