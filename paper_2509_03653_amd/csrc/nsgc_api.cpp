@@ -25,7 +25,8 @@ hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t
                             uint32_t grid, size_t lds, hipStream_t s);
 hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_buckets, uint32_t grid,
                         size_t lds, hipStream_t s);
-hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
+hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t hist, uint32_t grid, size_t lds,
+                             hipStream_t s);
 hipError_t launch_order(const nsgc_dev_plan* P, hipStream_t s);
 hipError_t launch_finish(const nsgc_dev_plan* P, uint32_t grid, hipStream_t s);
 hipError_t launch_rowcol_ent(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
@@ -35,7 +36,7 @@ size_t lds_small_bytes(uint32_t slots_log2);
 size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2, uint32_t max_rc_buckets);
 size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_rc_buckets);
 size_t lds_rc_bytes(uint32_t slots_log2);
-size_t lds_links_wave_bytes();
+size_t lds_links_wave_bytes(uint32_t hist);
 hipError_t allow_large_lds(size_t bytes);
 hipError_t resident_blocks(int which, uint32_t tile_log2, size_t lds, int* blocks);
 }  // namespace nsgc
@@ -190,10 +191,18 @@ int take_stage(Slot* sl, size_t need, hipStream_t s, int* idx) {
   return NSGC_OK;
 }
 
+// The wavefront phase-B kernel's two sizes of per-wavefront row and column
+// counters: batches whose wavefront windows have at most 64 row and column
+// buckets get the smaller LDS footprint and more resident wavefronts.
+constexpr uint32_t kWaveHist[2] = {64 + 1, NSGC_WAVE_MAX_RC + 1};
+inline int wave_class(uint32_t rc_max) { return rc_max <= 64 ? 0 : 1; }
+
 struct Launch {
-  uint32_t grid_small, grid_part, grid_link, grid_rc, grid_linkw, grid_finish, grid_rce;  // persistent grids
+  uint32_t grid_small, grid_part, grid_link, grid_rc, grid_finish, grid_rce;  // persistent grids
+  uint32_t grid_linkw[2];                              // per wave_class
   bool combine;                                        // phase-B emission combines per id
-  size_t lds_small, lds_part, lds_link, lds_rc, lds_linkw, lds_rce;
+  size_t lds_small, lds_part, lds_link, lds_rc, lds_rce;
+  size_t lds_linkw[2];
   uint32_t max_link_buckets, max_rc_buckets;
 };
 
@@ -222,9 +231,9 @@ int launch_params(DevCtx* c, const nsgc_tune& t, Launch* out) {
   L.lds_part = lds_part_bytes(L.max_link_buckets, tile, L.max_rc_buckets);
   L.lds_link = lds_link_bytes(uint32_t(t.link_slots_log2), L.max_rc_buckets);
   L.lds_rc = lds_rc_bytes(uint32_t(t.rc_slots_log2));
-  L.lds_linkw = lds_links_wave_bytes();
+  for (int k = 0; k < 2; ++k) L.lds_linkw[k] = lds_links_wave_bytes(kWaveHist[k]);
   const size_t m = std::max(std::max(std::max(L.lds_small, L.lds_part), std::max(L.lds_link, L.lds_rc)),
-                            L.lds_linkw);
+                            L.lds_linkw[1]);
   if (m > c->lds_limit) return NSGC_ERR_INVALID_ARG;
   int rc;
   const int want = t.blocks_per_cu;
@@ -236,7 +245,9 @@ int launch_params(DevCtx* c, const nsgc_tune& t, Launch* out) {
   if ((rc = resident_cap(c, 3, tile, L.lds_rc, want, &L.grid_rc)) != NSGC_OK) return rc;
   // the wavefront kernel runs four small workgroups per CU for every one of
   // the workgroup kernels' 512-thread workgroups
-  if ((rc = resident_cap(c, 5, tile, L.lds_linkw, 4 * want, &L.grid_linkw)) != NSGC_OK) return rc;
+  for (int k = 0; k < 2; ++k)
+    if ((rc = resident_cap(c, 5, tile, L.lds_linkw[k], 4 * want, &L.grid_linkw[k])) != NSGC_OK)
+      return rc;
   L.grid_finish = uint32_t(c->cus) * 4;
   // the entity outputs' phase C (two tables per workgroup)
   L.lds_rce = lds_rc_ent_bytes(uint32_t(std::min(t.rc_slots_log2, 12)));
@@ -249,11 +260,12 @@ int launch_params(DevCtx* c, const nsgc_tune& t, Launch* out) {
 }
 
 // Which kernels a plan needs: bit 0 the small-window kernel, bit 1 phases A
-// and C, bit 2 phase B by workgroups, bit 3 phase B by wavefronts.
-constexpr int kVariants = 16;
+// and C, bit 2 phase B by workgroups, bit 3 phase B by wavefronts, bit 4 the
+// wavefront kernel's larger counters (see wave_class).
+constexpr int kVariants = 32;
 int plan_variant(const HostPlan& hp) {
   return (hp.small.empty() ? 0 : 1) | (hp.win.empty() ? 0 : 2) | (hp.itemsBb ? 4 : 0) |
-         (hp.itemsBw ? 8 : 0);
+         (hp.itemsBw ? 8 : 0) | (hp.itemsBw && wave_class(hp.wave_rc_max) ? 16 : 0);
 }
 
 // Enqueue the kernels of one uploaded plan.  With `fixed_grid` (graph
@@ -286,8 +298,11 @@ int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch
     NSGC_HIP(launch_partition(dplan, tile_log2, L.max_link_buckets, grid(hp.itemsA, L.grid_part),
                               L.lds_part, s));
   NSGC_HIP(mark(2));
-  if (linkw)
-    NSGC_HIP(launch_links_wave(dplan, grid((hp.itemsBw + 3) / 4, L.grid_linkw), L.lds_linkw, s));
+  if (linkw) {
+    const int wc = fixed_grid ? ((variant & 16) ? 1 : 0) : wave_class(hp.wave_rc_max);
+    NSGC_HIP(launch_links_wave(dplan, kWaveHist[wc], grid((hp.itemsBw + 3) / 4, L.grid_linkw[wc]),
+                               L.lds_linkw[wc], s));
+  }
   if (linkb)
     NSGC_HIP(launch_links(dplan, L.combine && !hp.entity, L.max_rc_buckets,
                           grid(hp.itemsBb, L.grid_link), L.lds_link, s));

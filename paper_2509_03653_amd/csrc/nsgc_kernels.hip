@@ -778,8 +778,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 
     // Link table of sweep `sw` of 2^logS.  With `cap`, every packet of the
     // bucket (of any sweep) is also counted in histR / histC by its row and
-    // column bucket.
-    auto build = [&](uint32_t logS, uint32_t sw, bool cap) {
+    // column bucket.  An insert gives up after `probes` probes.
+    auto build = [&](uint32_t logS, uint32_t sw, bool cap, uint32_t probes) {
       if (threadIdx.x < 2) misc[threadIdx.x] = 0;
       __syncthreads();
       gather_by_wave<LINK_MAXU>(nt, seg, [&](const auto& pos, const auto& okin) {
@@ -827,7 +827,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
         }
         int slot[U];
         bool fresh[U];
-        if (!cas_insert<U>(tk, S - 1, key, h, ok, slot, fresh, NSGC_MAX_PROBES))
+        if (!cas_insert<U>(tk, S - 1, key, h, ok, slot, fresh, probes))
           lds_store(&misc[0], 1);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1095,7 +1095,9 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
         }
 #pragma nounroll
         for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
-          build(logS, sw, logS > 0 && sw == 0 && passes == 1);
+          // pass 1 rebuilds sweeps that pass 0 showed to fit: it may probe the
+          // whole table (chains depend on the order of concurrent inserts)
+          build(logS, sw, logS > 0 && sw == 0 && passes == 1, pass ? S : NSGC_MAX_PROBES);
           if (misc[0]) { failed = true; reset(); break; }
           if (pass == 1) {
             emit();
@@ -1198,15 +1200,20 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 constexpr int WAVE_NT = 256;                 // threads per workgroup
 constexpr int WAVE_WPB = WAVE_NT / 64;       // wavefronts per workgroup
 constexpr uint32_t WAVE_SLOTS = 1u << NSGC_WAVE_SLOTS_LOG2;
-constexpr uint32_t WAVE_HIST = NSGC_WAVE_MAX_RC + 1;   // counters per view
+
 static_assert(WAVE_SLOTS <= 65536, "slots are listed as 16-bit indices");
 
-// LDS of one wavefront: keys, counts, the occupied-slot list, the row and
-// column bucket counters.
-constexpr size_t WAVE_LDS = size_t(WAVE_SLOTS) * 8 + size_t(WAVE_SLOTS) * 4 +
-                            size_t(WAVE_SLOTS) * 2 + 2 * size_t(WAVE_HIST) * 4 + 64;
+// LDS of one wavefront: keys, counts, the row and column bucket counters
+// (`hist` per view: one more than the launch's largest row or column bucket
+// count, so that batches of small windows fit more wavefronts per CU) and the
+// occupied-slot list.
+__host__ __device__ constexpr size_t wave_lds_stride(uint32_t hist) {
+  return (size_t(WAVE_SLOTS) * 8 + size_t(WAVE_SLOTS) * 4 + 2 * size_t(hist) * 4 +
+          size_t(WAVE_SLOTS) * 2 + 15) &
+         ~size_t(15);
+}
 
-size_t lds_links_wave_bytes() { return size_t(WAVE_WPB) * ((WAVE_LDS + 15) & ~size_t(15)); }
+size_t lds_links_wave_bytes(uint32_t hist) { return size_t(WAVE_WPB) * wave_lds_stride(hist); }
 
 __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1270,14 +1277,14 @@ struct WaveQueue {
   }
 };
 
-__global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P) {
+__global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32_t hist) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t w = uniform(threadIdx.x >> 6), lane = lane_id();
-  unsigned char* p = smem + size_t(w) * ((WAVE_LDS + 15) & ~size_t(15));
+  unsigned char* p = smem + size_t(w) * wave_lds_stride(hist);
   u64* tk = reinterpret_cast<u64*>(p);             p += size_t(WAVE_SLOTS) * 8;
   uint32_t* tc = reinterpret_cast<uint32_t*>(p);   p += size_t(WAVE_SLOTS) * 4;
-  uint32_t* histR = reinterpret_cast<uint32_t*>(p);  p += size_t(WAVE_HIST) * 4;
-  uint32_t* histC = reinterpret_cast<uint32_t*>(p);  p += size_t(WAVE_HIST) * 4;
+  uint32_t* histR = reinterpret_cast<uint32_t*>(p);  p += size_t(hist) * 4;
+  uint32_t* histC = reinterpret_cast<uint32_t*>(p);  p += size_t(hist) * 4;
   uint16_t* occ = reinterpret_cast<uint16_t*>(p);
   constexpr uint32_t S = WAVE_SLOTS;
 
@@ -1315,9 +1322,11 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P) {
 
     uint32_t n = 0;        // occupied slots (uniform)
     uint32_t special = 0;  // packets of the key equal to the empty marker (uniform)
+    uint32_t links = 0, sum = 0, mx = 0;   // the bucket's statistics
 
-    // Link table of sweep `sw` of 2^logS; false if an insert gave up.
-    auto build = [&](uint32_t logS, uint32_t sw) -> bool {
+    // Link table of sweep `sw` of 2^logS; false if an insert gave up (after
+    // `probes` probes).
+    auto build = [&](uint32_t logS, uint32_t sw, uint32_t probes) -> bool {
       n = 0;
       special = 0;
       bool gave_up = false;
@@ -1376,7 +1385,7 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P) {
           }
           int slot[LINK_MAXU];
           bool fresh[LINK_MAXU];
-          if (!cas_insert<LINK_MAXU>(tk, S - 1, key, h, ok, slot, fresh, NSGC_MAX_PROBES))
+          if (!cas_insert<LINK_MAXU>(tk, S - 1, key, h, ok, slot, fresh, probes))
             gave_up = true;
 #pragma unroll
           for (int u = 0; u < LINK_MAXU; ++u)
@@ -1403,15 +1412,23 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P) {
       wave_fence();
     };
 
+    // the statistics of the table's links and their entries per row and
+    // column bucket
     auto count = [&]() {
       for (uint32_t i = lane; i < n; i += 64) {
         const uint32_t s = occ[i];
+        const uint32_t c = tc[s];
+        sum += c;
+        mx = max(mx, c);
         const u64 key = tk[s];
-        const uint32_t parts = entry_parts(tc[s], 1);
+        const uint32_t parts = entry_parts(c, 1);
         lds_add(&histR[top32(uint32_t(key >> 32), W.logR)], parts);
         lds_add(&histC[top32(uint32_t(key), W.logC)], parts);
       }
+      links += n + (special ? 1u : 0u);
       if (lane == 0 && special) {
+        sum += special;
+        mx = max(mx, special);
         const uint32_t parts = entry_parts(special, 1);
         lds_add(&histR[top32(EMPTY32, W.logR)], parts);
         lds_add(&histC[top32(EMPTY32, W.logC)], parts);
@@ -1463,7 +1480,6 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P) {
       wave_fence();
     };
 
-    uint32_t links = 0, sum = 0, mx = 0;
     bool abandoned = false;
     for (uint32_t logS = 0;; ++logS) {
       if (logS > P->max_sweeps_log2) { abandoned = true; break; }
@@ -1476,18 +1492,10 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P) {
       for (uint32_t pass = 0; pass < passes && !failed; ++pass) {
         if (pass == 1) publish();
         for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
-          if (!build(logS, sw)) { failed = true; reset(); break; }
+          // pass 1 rebuilds sweeps that pass 0 showed to fit: it may probe the
+          // whole table (chains depend on the order of concurrent inserts)
+          if (!build(logS, sw, pass ? S : NSGC_MAX_PROBES)) { failed = true; reset(); break; }
           if (pass == 1) { emit(); continue; }
-          for (uint32_t i = lane; i < n; i += 64) {
-            const uint32_t c = tc[occ[i]];
-            sum += c;
-            mx = max(mx, c);
-          }
-          links += n + (special ? 1u : 0u);
-          if (lane == 0 && special) {
-            sum += special;
-            mx = max(mx, special);
-          }
           count();
           if (logS == 0) {
             publish();
@@ -1853,8 +1861,9 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol_ent(nsgc_dev_plan* P) {
     const uint32_t logK = W.logR;
     const NSGC_GLOBAL uint32_t* rec = gptr(P->lbmeta) + W.lbmeta;
 
-    // Table of view v (0 rows, 1 columns) for sweep sw of 2^logS.
-    auto build = [&](int v, uint32_t logS, uint32_t sw) {
+    // Table of view v (0 rows, 1 columns) for sweep sw of 2^logS; an insert
+    // gives up after `probes` probes.
+    auto build = [&](int v, uint32_t logS, uint32_t sw, uint32_t probes) {
       const NSGC_GLOBAL uint32_t* st0 = rec + B + (v == 0 ? u64(k) * B : u64(R + 1) * B + u64(k) * B);
       const NSGC_GLOBAL uint32_t* st1 = st0 + B;
       const NSGC_GLOBAL u64* em = gptr(v == 0 ? P->emit_row : P->emit_col) + W.ws;
@@ -1892,7 +1901,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol_ent(nsgc_dev_plan* P) {
         }
         int slot[U];
         bool fresh[U];
-        if (!cas_insert<U>(tk, S - 1, id, h, ok, slot, fresh, NSGC_MAX_PROBES))
+        if (!cas_insert<U>(tk, S - 1, id, h, ok, slot, fresh, probes))
           lds_store(&misc[0], 1);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1961,11 +1970,11 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol_ent(nsgc_dev_plan* P) {
       __syncthreads();
     };
 
-    auto sweep = [&](uint32_t logS, uint32_t sw) -> bool {
+    auto sweep = [&](uint32_t logS, uint32_t sw, uint32_t probes) -> bool {
       if (threadIdx.x < 6) misc[threadIdx.x] = 0;
       __syncthreads();
-      build(0, logS, sw);
-      build(1, logS, sw);   // ends with a barrier
+      build(0, logS, sw, probes);
+      build(1, logS, sw, probes);   // ends with a barrier
       return misc[0] == 0;
     };
 
@@ -1976,14 +1985,17 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_rowcol_ent(nsgc_dev_plan* P) {
       nr = mr = mf = nc = mc = mg = uni = 0;
       bool failed = false;
       for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
-        if (!sweep(logS, sw)) { failed = true; harvest(false, false); break; }
+        if (!sweep(logS, sw, NSGC_MAX_PROBES)) { failed = true; harvest(false, false); break; }
         harvest(true, logS == 0);
       }
       if (!failed) break;
     }
-    if (!abandoned && logS > 0)   // the lists over the sweeps now known to fit
+    // The lists over the sweeps now known to fit.  Probe chains depend on the
+    // order of concurrent inserts, so a rebuild may probe the whole table: it
+    // then always succeeds, as each sweep holds at most S ids.
+    if (!abandoned && logS > 0)
       for (uint32_t sw = 0; sw < (1u << logS); ++sw) {
-        sweep(logS, sw);
+        sweep(logS, sw, S);
         harvest(false, true);
       }
     uint32_t zero = 0;
@@ -2118,8 +2130,10 @@ hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_bu
   return hipGetLastError();
 }
 
-hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_links_wave, dim3(grid), dim3(WAVE_NT), lds, s, const_cast<nsgc_dev_plan*>(P));
+hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t hist, uint32_t grid, size_t lds,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_links_wave, dim3(grid), dim3(WAVE_NT), lds, s, const_cast<nsgc_dev_plan*>(P),
+                     hist);
   return hipGetLastError();
 }
 

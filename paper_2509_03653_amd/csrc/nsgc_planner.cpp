@@ -97,6 +97,7 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
   p->mapBb.clear();
   p->mapBw.clear();
   p->itemsBb = p->itemsBw = 0;
+  p->wave_rc_max = 0;
   p->tier.assign(size_t(num_windows), 0);
   p->ws_elems = p->tilemeta_words = p->lbmeta_words = 0;
   p->tile_log2 = uint32_t(tune.tile_log2);
@@ -146,6 +147,7 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
       if (lw <= capB) {
         d.logB = uint8_t(lw);
         d.wave = 1;
+        p->wave_rc_max = std::max(p->wave_rc_max, 1u << std::max(d.logR, d.logC));
       }
     }
     d.ntiles = uint32_t((n + tile - 1) / tile);

@@ -36,6 +36,7 @@ struct HostPlan {
   std::vector<uint32_t> itemwinB, itemwinC;   // window of each phase-B / phase-C item
   std::vector<uint32_t> mapBb, mapBw;         // phase-B items by kernel (empty: identity)
   uint32_t itemsBb = 0, itemsBw = 0;
+  uint32_t wave_rc_max = 0;    // largest row or column bucket count of a wavefront window
   int64_t ws_elems = 0;        // packets of the partitioned windows
   int64_t tilemeta_words = 0;  // u32 words of tile bucket starts
   int64_t lbmeta_words = 0;    // u32 words of link-bucket records
