@@ -264,6 +264,45 @@ def large_leg(nsgc, torch, seed, steps=5):
                          "traffic": measured_traffic("skewed_large", dom)}}
 
 
+def single_large_leg(nsgc, torch, seed, steps=3):
+    """One window of 2^30 skewed packets (the whole capture as one graph):
+    the large-window tier, direct batched form, per-phase times; checked by
+    the statistics' invariants and the src/dst swap relation first (the
+    oracle would need minutes for it)."""
+    import synth
+    wl = synth.skewed_large(seed=seed, num_windows=1, log2_window=30)
+    src, dst = wl.generate()
+    off = wl.offsets
+    n = wl.num_packets
+    s = torch.from_numpy(src.view(np.int32)).cuda()
+    d = torch.from_numpy(dst.view(np.int32)).cuda()
+    del src, dst
+    stream = torch.cuda.current_stream()
+    fwd = nsgc.window_stats(s, d, off, stream=stream)
+    rev = nsgc.window_stats(d, s, off, stream=stream)
+    torch.cuda.synchronize()
+    a = fwd.cpu().numpy().view(np.uint64)[0]
+    b = rev.cpu().numpy().view(np.uint64)[0]
+    ok = (int(a[0]) == n and np.array_equal(b, a[[0, 1, 2, 6, 7, 8, 3, 4, 5]])
+          and a[1] <= a[0] and a[3] <= a[1] and a[6] <= a[1] and a[4] <= a[0]
+          and a[5] <= a[6] and a[8] <= a[3] and a[2] <= min(a[4], a[7]))
+    if not ok:
+        raise SystemExit("invariant check failed on the single 2^30-packet window")
+    out = torch.empty((1, 9), dtype=torch.int64, device="cuda")
+    ms = time_loop(lambda i: nsgc.window_stats(s, d, off, out=out, stream=stream), steps, 1,
+                   stream)
+    _, ph = nsgc.window_stats_timed(s, d, off, out=out, stream=stream)
+    del s, d
+    torch.cuda.empty_cache()
+    nsgc.release()
+    return {"workload": "1 window x 2^30 packets, 10% from one super-source, 1% to one "
+                        "super-destination, rest Zipf(1.3) over 2^26 addresses",
+            "packets": n, "tier": "large (radix sort)", "ms_per_call": ms,
+            "packets_per_s": n / (ms * 1e-3), "phase_ms": ph,
+            "algorithmic_frac": 8 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "stats": [int(x) for x in a]}
+
+
 def cpu_baseline(src, dst, offsets, budget_s: float):
     """The oracle on the host cores: the whole batch, repeated while within
     budget; for batches too large for the budget, consecutive groups of
@@ -579,6 +618,7 @@ def main():
         torch.cuda.empty_cache()
         nsgc.release()
         extra["skewed_2e30"] = large_leg(nsgc, torch, args.seed)
+        extra["single_window_2e30"] = single_large_leg(nsgc, torch, args.seed)
 
     value = P / (ms_graph * 1e-3)
     line = {

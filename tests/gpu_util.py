@@ -24,6 +24,8 @@ def gpu_stats(src, dst, offsets, form="batched", graph=None):
         out = nsgc.window_stats(s, d, off)
     elif form == "plain":
         out = nsgc.window_stats_plain(s, d, off)
+    elif form == "noalloc":
+        out = nsgc.window_stats_noalloc(s, d, off)
     elif form == "graph":
         g = graph or nsgc.Graph(max(int(off[-1] - off[0]), 1), max(len(off) - 1, 1))
         out = g.launch(s, d, off)

@@ -4,8 +4,8 @@ With the tier's threshold lowered to its minimum (2^20 packets) it is
 compared bit for bit with the oracle on windows of every kind: heavy-tailed,
 skewed with a super-source and a super-destination, tiny alphabets (long
 runs of one link), a bijection (no repeats), addresses whose hashed form is
-all ones, and batches that mix it with the other tiers, in the batched, plain
-and timed forms.  At the default threshold it takes a single window of 2^26
+all ones, and batches that mix it with the other tiers, in the batched,
+plain, fixed-scratch and timed forms.  At the default threshold it takes a single window of 2^26
 packets, compared in full with the oracle, and a single window of 2^30
 packets (the whole capture of the paper as one window), checked by the exact
 invariants and the src/dst swap (Table III caption: the reverse queries swap
@@ -66,7 +66,7 @@ def test_large_tier_every_kind_of_window():
         p = nsgc.plan_inspect(off)
         assert int(p["tier"][0]) == 3
         want = oracle.window_stats(src, dst, off)
-        for form in ("batched", "plain"):
+        for form in ("batched", "plain", "noalloc"):
             say(f"[gpu] large tier {name} {form}")
             assert_same(gpu_stats(src, dst, off, form), want, f"large {name} {form}")
 
@@ -139,5 +139,31 @@ def test_single_window_2e30_invariants_and_swap():
     invariants(rev, [n])
     np.testing.assert_array_equal(rev[0], fwd[0][[0, 1, 2, 6, 7, 8, 3, 4, 5]])
     del s, d
+    torch.cuda.empty_cache()
+    nsgc.release()
+
+
+def test_single_source_2e28_star():
+    # every packet from one source to a distinct destination: a star whose
+    # statistics are known in closed form, and its reverse
+    import torch
+
+    import paper_2509_03653_amd as nsgc
+    n = 1 << 28
+    src = np.full(n, 0x0A000001, np.uint32)
+    dst = np.arange(n, dtype=np.uint32)
+    off = np.array([0, n], np.int64)
+    assert int(nsgc.plan_inspect(off)["tier"][0]) == 3
+    say(f"[gpu] star of {n} distinct links")
+    s, d = to_gpu(src), to_gpu(dst)
+    del src, dst
+    out = nsgc.window_stats(s, d, off)
+    rev = nsgc.window_stats(d, s, off)
+    torch.cuda.synchronize()
+    want = np.array([[n, n, 1, 1, n, n, n, 1, 1]], np.uint64)
+    assert_same(out.cpu().numpy().view(np.uint64), want, "one-source window")
+    assert_same(rev.cpu().numpy().view(np.uint64), want[:, [0, 1, 2, 6, 7, 8, 3, 4, 5]],
+                "one-destination window")
+    del s, d, out, rev
     torch.cuda.empty_cache()
     nsgc.release()
