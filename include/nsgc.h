@@ -40,7 +40,10 @@
  *   - stream: the HIP stream the work is enqueued on (0 = null stream).  The
  *     call returns after enqueueing; results are valid once the stream has
  *     reached that point.  Input buffers must stay alive and unmodified until
- *     then.
+ *     then.  One exception: a batch with a window of the large-window tier
+ *     (nsgc_tune.large_min_log2) waits once per such window for the stream,
+ *     to read back the window's link count, so the call returns only after
+ *     the work enqueued before that point has run.
  *   - Argument errors are reported synchronously with nothing enqueued and
  *     out_stats untouched.  A HIP runtime failure returns NSGC_ERR_HIP and
  *     nsgc_last_hip_error() gives the hipError_t.
@@ -220,8 +223,9 @@ typedef struct nsgc_tune {
   nsgc_tune_class cls[33];
   int32_t large_min_log2;   /* windows of at least 2^k packets are computed by
                                sorting instead of hash partitioning, one window
-                               at a time (20..33; 33 turns the tier off; the
-                               graph form and the entity outputs never use it) */
+                               at a time, with one wait for the stream each
+                               (20..33; 33 turns the tier off; the graph form
+                               and the entity outputs never use it) */
 } nsgc_tune;
 
 /* Current tuning of the calling process (defaults until set). */

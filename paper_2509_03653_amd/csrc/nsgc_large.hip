@@ -195,26 +195,6 @@ __global__ __launch_bounds__(LT) void k_lw_cols(const uint32_t* __restrict__ cs,
   }
 }
 
-// Column elements past the links (their number is known on the device only)
-// are set to all ones, so that a stable sort by the high half keeps them last.
-__global__ __launch_bounds__(LT) void k_lw_fill_tail(u64* __restrict__ c, u64 n,
-                                                     const uint32_t* __restrict__ nl) {
-  const uint32_t m = *nl;
-  for (u64 i = m + u64(blockIdx.x) * LT + threadIdx.x; i < n; i += u64(gridDim.x) * LT)
-    c[i] = ~0ull;
-}
-
-// Zero both arrays past the links, so that scans over all n slots count links only.
-__global__ __launch_bounds__(LT) void k_lw_clear_tail(uint32_t* __restrict__ a,
-                                                      uint32_t* __restrict__ b, u64 n,
-                                                      const uint32_t* __restrict__ nl) {
-  const uint32_t m = *nl;
-  for (u64 i = m + u64(blockIdx.x) * LT + threadIdx.x; i < n; i += u64(gridDim.x) * LT) {
-    a[i] = 0;
-    b[i] = 0;
-  }
-}
-
 // Copy two device counts (scan totals whose scratch is about to be reused).
 __global__ void k_lw_save(const uint32_t* nl, const uint32_t* nr, uint32_t* to) {
   if (threadIdx.x == 0) {
@@ -284,27 +264,29 @@ hipError_t large_window_stats(const uint32_t* src, const uint32_t* dst, u64 n, v
   hipLaunchKernelGGL(k_lw_rows, dim3(g), dim3(LT), 0, s, Dv, A, nl, nr, n, out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
 
-  // Columns: sort the column elements by their high half.  The number of
-  // links is only known on the device, so all n slots are sorted: those past
-  // the links are set to all ones and sort last.
-  hipLaunchKernelGGL(k_lw_fill_tail, dim3(g), dim3(LT), 0, s, O, n, nl);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   // keep the link and source counts: the scratch that holds them is reused
   hipLaunchKernelGGL(k_lw_save, dim3(1), dim3(64), 0, s, nl, nr, counts);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const uint32_t* nl2 = counts;
   const uint32_t* nr2 = counts + 1;
+  // Columns: sort the column elements by their high half.  Only the first
+  // `links` slots hold elements; the count is read back (one wait for the
+  // stream) so that the sort and the scans cover just those, a small share of
+  // the window's packets when links repeat.
+  uint32_t links = 0;
+  if ((e = hipMemcpyAsync(&links, counts, sizeof links, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  if (links == 0 || links > n) return hipErrorInvalidValue;
+  const uint32_t gl = uint32_t(std::min<u64>((u64(links) + LT - 1) / LT, grid));
   u64* C = nullptr;
-  if ((e = radix_sort_u64(O, S, n, 32, 64, scratch, grid, s, &C)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lw_colflags, dim3(g), dim3(LT), 0, s, C, nl2, A, Bv);
+  if ((e = radix_sort_u64(O, S, links, 32, 64, scratch, grid, s, &C)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lw_colflags, dim3(gl), dim3(LT), 0, s, C, nl2, A, Bv);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // scan only the link prefix: the arrays past it are never read
-  hipLaunchKernelGGL(k_lw_clear_tail, dim3(g), dim3(LT), 0, s, A, Bv, n, nl2);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = exclusive_scan_u32(A, n, scratch, s)) != hipSuccess) return e;
-  if ((e = exclusive_scan_u32(Bv, n, scratch2, s)) != hipSuccess) return e;
-  const uint32_t* nc = scan_total(scratch, n);
-  hipLaunchKernelGGL(k_lw_colcompact, dim3(g), dim3(LT), 0, s, C, A, Bv, Cv, Dv, nl2, nc, n);
+  if ((e = exclusive_scan_u32(A, links, scratch, s)) != hipSuccess) return e;
+  if ((e = exclusive_scan_u32(Bv, links, scratch2, s)) != hipSuccess) return e;
+  const uint32_t* nc = scan_total(scratch, links);
+  hipLaunchKernelGGL(k_lw_colcompact, dim3(gl), dim3(LT), 0, s, C, A, Bv, Cv, Dv, nl2, nc, n);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_lw_cols, dim3(g), dim3(LT), 0, s, Cv, Dv, nc, out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
