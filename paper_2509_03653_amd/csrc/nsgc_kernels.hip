@@ -1342,21 +1342,45 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
         // walk the concatenation of the group's segments, 64 keys per chunk
         const uint32_t incl = wave_inclusive_scan(len);
         const uint32_t elems = uniform(readlane(incl, 63));
-        mb -= incl - len;                       // base minus exclusive prefix
+        const uint32_t start = incl - len;      // exclusive prefix: the segment's first element
+        const u64 nonempty = __ballot(len > 0);
+        mb -= start;                            // base minus exclusive prefix
         for (uint32_t v0 = 0; v0 < elems; v0 += 64 * LINK_MAXU) {
           u64 key[LINK_MAXU];
           uint32_t h[LINK_MAXU], add[LINK_MAXU];
           bool ok[LINK_MAXU];
 #pragma unroll
           for (int u = 0; u < LINK_MAXU; ++u) {
-            const uint32_t v = v0 + uint32_t(u) * 64u + lane;
-            uint32_t j = 0;
-#pragma unroll
-            for (uint32_t st = 32; st > 0; st >>= 1)
-              if (lane_take(incl, j + st - 1) <= v) j += st;
-            const u64 pos = ((u64(lane_take(uint32_t(mb >> 32), j)) << 32) |
-                             lane_take(uint32_t(mb), j)) + v;
+            const uint32_t vc = v0 + uint32_t(u) * 64u;   // the chunk's first element
+            const uint32_t v = vc + lane;
             ok[u] = v < elems;
+            u64 pos = 0;
+            if (vc < elems) {
+              // the non-empty segments holding the chunk's first and last elements
+              const uint32_t last = min(vc + 63u, elems - 1u);
+              const int jlo = 63 - __clzll(__ballot(start <= vc) & nonempty);
+              const int jhi = 63 - __clzll(__ballot(start <= last) & nonempty);
+              if (jhi - jlo <= 8) {
+                // few segments: walk them with uniform lane reads (no LDS)
+                u64 base = (u64(readlane(uint32_t(mb >> 32), jlo)) << 32) |
+                           readlane(uint32_t(mb), jlo);
+                for (int k = jlo + 1; k <= jhi; ++k) {
+                  const uint32_t sk = readlane(start, k);
+                  const u64 bk = (u64(readlane(uint32_t(mb >> 32), k)) << 32) |
+                                 readlane(uint32_t(mb), k);
+                  if (v >= sk) base = bk;
+                }
+                pos = base + v;
+              } else {
+                // many short segments: each lane finds its own by a binary search
+                uint32_t j = 0;
+#pragma unroll
+                for (uint32_t st = 32; st > 0; st >>= 1)
+                  if (lane_take(incl, j + st - 1) <= v) j += st;
+                pos = ((u64(lane_take(uint32_t(mb >> 32), j)) << 32) |
+                       lane_take(uint32_t(mb), j)) + v;
+              }
+            }
             const u64 kk = keys[ok[u] ? pos : 0ull];   // position 0 exists; masked below
             key[u] = ok[u] ? kk : 0ull;
           }
