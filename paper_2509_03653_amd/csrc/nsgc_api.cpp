@@ -854,6 +854,9 @@ struct nsgc_graph {
     char* stage = nullptr;
     hipGraph_t graph[kVariants] = {};     // indexed by plan variant (see plan_variant)
     hipGraphExec_t exec[kVariants] = {};
+    // the plan-upload node of each variant, resized to the plan at every
+    // launch (null: the node keeps uploading plan_cap bytes)
+    hipGraphNode_t copy[kVariants] = {};
     hipEvent_t done = nullptr;
     hipStream_t stream = nullptr;  // stream of the last launch
     bool used = false;
@@ -885,6 +888,22 @@ int capture_instance(nsgc_graph* g, nsgc_graph::Inst& in, int variant) {
   if (e2 != hipSuccess) return hip_fail(e2);
   in.graph[variant] = graph;
   NSGC_HIP(hipGraphInstantiate(&in.exec[variant], graph, nullptr, nullptr, 0));
+  // The plan-upload node, so that each launch copies only its plan: the
+  // bound it was captured with is sized for the graph's largest batch.
+  size_t nn = 0;
+  if (hipGraphGetNodes(graph, nullptr, &nn) == hipSuccess && nn > 0) {
+    std::vector<hipGraphNode_t> nodes(nn);
+    if (hipGraphGetNodes(graph, nodes.data(), &nn) == hipSuccess) {
+      for (size_t i = 0; i < nn; ++i) {
+        hipGraphNodeType type;
+        if (hipGraphNodeGetType(nodes[i], &type) == hipSuccess && type == hipGraphNodeTypeMemcpy) {
+          in.copy[variant] = nodes[i];
+          break;
+        }
+      }
+    }
+  }
+  (void)hipGetLastError();   // no node found: every launch uploads plan_cap bytes
   return NSGC_OK;
 }
 
@@ -990,6 +1009,9 @@ int nsgc_graph_launch(nsgc_graph* g, const uint32_t* src, const uint32_t* dst,
   // other instance's last one waits (on the device) for that launch to end.
   const nsgc_graph::Inst& other = g->inst[g->next ^ 1];
   if (other.used && other.stream != s) NSGC_HIP(hipStreamWaitEvent(s, other.done, 0));
+  if (in.copy[variant])   // upload this plan's bytes only
+    NSGC_HIP(hipGraphExecMemcpyNodeSetParams1D(in.exec[variant], in.copy[variant], in.plan_dev,
+                                               in.stage, hp.plan_bytes(), hipMemcpyHostToDevice));
   NSGC_HIP(hipGraphLaunch(in.exec[variant], s));
   NSGC_HIP(hipEventRecord(in.done, s));
   in.stream = s;
