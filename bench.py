@@ -109,6 +109,22 @@ def tune_with(nsgc, spec: str):
     return t
 
 
+def synth_workload(name, seed):
+    import synth
+    return synth.WORKLOADS[name](seed=seed)
+
+
+def stream_copy_gbs(torch, stream, nbytes=CALIB_BYTES, reps=5):
+    """Device-to-device copy bandwidth (bytes read + written per second) of a
+    1 GiB buffer: what a plain streaming kernel reaches on this device."""
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    ms = time_loop(lambda i: b.copy_(a), reps, 2, stream)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def make_inputs(args):
     import synth
     wl = synth.WORKLOADS[args.workload](seed=args.seed)
@@ -589,6 +605,21 @@ def main():
     ms_graph = time_loop(step_graph, args.steps, args.warmup, stream)
     ms_direct = time_loop(step_direct, args.steps, args.warmup, stream)
     ms_plain = time_loop(step_plain, max(args.steps // 4, 5), max(args.warmup // 2, 2), stream)
+    # warm: the same input copy every step (its keys may stay in the 256 MB cache)
+    ms_warm = time_loop(lambda i: graph.launch(ss[0], dd[0], off, out=out, stream=stream),
+                        args.steps, args.warmup, stream)
+    copy_gbs = stream_copy_gbs(torch, stream)
+    seed_ms = {str(args.seed): ms_graph}
+    if args.workload == "zipf_batch" and not args.tune and not args.autotune:
+        for sd in (args.seed + 1, args.seed + 2):   # two more seeds of the same workload
+            wl2 = synth_workload(args.workload, sd)
+            s2, d2 = wl2.generate()
+            a2 = torch.from_numpy(s2.view(np.int32)).cuda()
+            b2 = torch.from_numpy(d2.view(np.int32)).cuda()
+            seed_ms[str(sd)] = time_loop(
+                lambda i: graph.launch(a2, b2, wl2.offsets, out=out, stream=stream),
+                args.steps, args.warmup, stream)
+            del a2, b2
 
     # per-kernel HIP-event times on the launch stream
     phases = {k: [] for k in nsgc.PHASES}
@@ -644,6 +675,11 @@ def main():
         "batched_over_plain": ms_plain / ms_graph,
         "step_algorithmic_GBs": alg / (ms_graph * 1e-3) / 1e9,
         "step_roofline_frac": alg / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "warm_ms_per_step": ms_warm,
+        "stream_copy_GBs": copy_gbs,
+        "step_frac_of_stream_copy": alg / (ms_graph * 1e-3) / 1e9 / copy_gbs,
+        "seed_ms_per_step": seed_ms,
+        "seed_median_packets_per_s": P / (float(np.median(list(seed_ms.values()))) * 1e-3),
         "phase_ms": phase_ms,
         "roofline": {"bound": "hbm", "phase": dominant, "kernels": PHASE_KERNELS[dominant],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
