@@ -1619,7 +1619,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_order(nsgc_dev_plan* P) {
 
 size_t lds_rc_bytes(uint32_t slots_log2) {
   const size_t S = size_t(1) << slots_log2;
-  return align16(S * 4) * 3 + 256;
+  return align16(S * 4) + align16(S * 8) + 256;
 }
 
 __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_rowcol(nsgc_dev_plan* P) {
@@ -1627,8 +1627,9 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
   const uint32_t S = 1u << P->rc_slots_log2;
   unsigned char* p = smem;
   uint32_t* tk = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
-  uint32_t* ta = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
-  uint32_t* tb = reinterpret_cast<uint32_t*>(p);       p += align16(S * 4);
+  // per slot: links << 32 | packets, one 64-bit add per entry (neither half
+  // carries: a bucket's packets and links stay below 2^32)
+  u64* tv = reinterpret_cast<u64*>(p);                 p += align16(S * 8);
   struct { uint32_t* red; } st;                        // reduction scratch (in misc)
   uint32_t* misc = reinterpret_cast<uint32_t*>(p);     // [0] fail flag, [2,3] special id,
                                                        // [7] queue slot
@@ -1636,8 +1637,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
 
   for (uint32_t i = threadIdx.x; i < S; i += NSGC_BLOCK) {
     tk[i] = EMPTY32;
-    ta[i] = 0;
-    tb[i] = 0;
+    tv[i] = 0;
   }
 
   const uint32_t items = P->itemsC;
@@ -1708,11 +1708,11 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
       for (uint32_t i = threadIdx.x * 4; i < S; i += NSGC_BLOCK * 4) {
         const v4u32 k4 = *reinterpret_cast<const v4u32*>(tk + i);
         if (take) {
-          const v4u32 a4 = *reinterpret_cast<const v4u32*>(ta + i);
-          const v4u32 b4 = *reinterpret_cast<const v4u32*>(tb + i);
+          const v4u32 v01 = *reinterpret_cast<const v4u32*>(tv + i);       // slots i, i + 1
+          const v4u32 v23 = *reinterpret_cast<const v4u32*>(tv + i + 2);   // slots i + 2, i + 3
           const uint32_t ks[4] = {k4.x, k4.y, k4.z, k4.w};
-          const uint32_t as[4] = {a4.x, a4.y, a4.z, a4.w};
-          const uint32_t bs[4] = {b4.x, b4.y, b4.z, b4.w};
+          const uint32_t as[4] = {v01.x, v01.z, v23.x, v23.z};   // packets
+          const uint32_t bs[4] = {v01.y, v01.w, v23.y, v23.w};   // links
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             if (ks[j] != EMPTY32) {
@@ -1723,8 +1723,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
           }
         }
         *reinterpret_cast<v4u32*>(tk + i) = empty4;
-        *reinterpret_cast<v4u32*>(ta + i) = zero4;
-        *reinterpret_cast<v4u32*>(tb + i) = zero4;
+        *reinterpret_cast<v4u32*>(tv + i) = zero4;
+        *reinterpret_cast<v4u32*>(tv + i + 2) = zero4;
       }
       __syncthreads();
     };
@@ -1778,8 +1778,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (slot[u] >= 0) {
-            lds_add(&ta[slot[u]], pk[u]);
-            lds_add(&tb[slot[u]], ln[u]);
+            lds_add64(&tv[slot[u]], (u64(ln[u]) << 32) | pk[u]);
           }
         }
         (void)fresh;
