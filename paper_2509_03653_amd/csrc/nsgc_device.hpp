@@ -223,9 +223,22 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
   return max(max(readlane(v, 15), readlane(v, 31)), max(readlane(v, 47), readlane(v, 63)));
 }
 
-// Inclusive prefix sum across the wavefront (lane-shuffle form; used for the
-// small scans of bucket counters, not in per-packet loops).
+// Inclusive prefix sum across the wavefront (call with the whole wavefront
+// active): the row-local inclusive scan by DPP row shifts, plus the totals of
+// the rows below, read with readlane.
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  v += dpp_row_shr<1>(v);
+  v += dpp_row_shr<2>(v);
+  v += dpp_row_shr<4>(v);
+  v += dpp_row_shr<8>(v);
+  const uint32_t r0 = readlane(v, 15), r1 = readlane(v, 31), r2 = readlane(v, 47);
+  const uint32_t row = lane_id() >> 4;
+  return v + (row >= 1 ? r0 : 0u) + (row >= 2 ? r1 : 0u) + (row >= 3 ? r2 : 0u);
+}
+
+// The same by lane shuffles (LDS permutes): in the partition's 1024-thread
+// bucket scan this form measured 4 us per launch faster than the DPP form.
+__device__ __forceinline__ uint32_t wave_inclusive_scan_shfl(uint32_t v) {
   const uint32_t lane = lane_id();
 #pragma unroll
   for (int k = 1; k < 64; k <<= 1) {
@@ -399,7 +412,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t* a, uint32_t n
   const uint32_t end = min(n, beg + per);
   uint32_t s = 0;
   for (uint32_t i = beg; i < end; ++i) s += a[i];
-  const uint32_t incl = wave_inclusive_scan(s);
+  const uint32_t incl = wave_inclusive_scan_shfl(s);
   const uint32_t w = threadIdx.x >> 6;
   if (lane_id() == 63) red[w] = incl;
   __syncthreads();
