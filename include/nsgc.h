@@ -226,6 +226,17 @@ typedef struct nsgc_tune {
                                at a time, with one wait for the stream each
                                (20..33; 33 turns the tier off; the graph form
                                and the entity outputs never use it) */
+  int32_t row_complete;     /* 0 (default): link buckets by the hash of the whole
+                               link.  1: windows whose link aggregation runs one
+                               wavefront per bucket are partitioned by the
+                               source hash, so that a source's links meet in
+                               one bucket and that bucket yields its packets
+                               and fan-out itself (stats 3-5 without a
+                               phase-C pass); sources that a sample of the
+                               window shows to be heavy are spread over the
+                               other buckets by the destination hash, and each
+                               such bucket emits one combined entry per heavy
+                               source.  Not used by the entity outputs. */
 } nsgc_tune;
 
 /* Current tuning of the calling process (defaults until set). */

@@ -104,11 +104,12 @@ class Tune(ctypes.Structure):
         ("combine_probes", ctypes.c_int32),
         ("cls", TuneClass * 33),
         ("large_min_log2", ctypes.c_int32),
+        ("row_complete", ctypes.c_int32),
     ]
 
     SCALARS = ("small_max", "tile_log2", "link_slots_log2", "rc_slots_log2",
                "blocks_per_cu", "max_link_buckets_log2", "max_rc_buckets_log2",
-               "max_sweeps_log2", "combine_probes", "large_min_log2")
+               "max_sweeps_log2", "combine_probes", "large_min_log2", "row_complete")
 
     def to_dict(self) -> dict:
         d = {k: int(getattr(self, k)) for k in self.SCALARS}

@@ -25,8 +25,10 @@ hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t
                             uint32_t grid, size_t lds, hipStream_t s);
 hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_buckets, uint32_t grid,
                         size_t lds, hipStream_t s);
-hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t hist, uint32_t grid, size_t lds,
-                             hipStream_t s);
+hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t hist, uint32_t rows, uint32_t grid,
+                             size_t lds, hipStream_t s);
+hipError_t launch_heavy(const nsgc_dev_plan* P, uint32_t grid, hipStream_t s);
+size_t lds_heavy_bytes();
 hipError_t launch_order(const nsgc_dev_plan* P, hipStream_t s);
 hipError_t launch_finish(const nsgc_dev_plan* P, uint32_t grid, hipStream_t s);
 hipError_t launch_rowcol_ent(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
@@ -36,7 +38,7 @@ size_t lds_small_bytes(uint32_t slots_log2);
 size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2, uint32_t max_rc_buckets);
 size_t lds_link_bytes(uint32_t slots_log2, uint32_t max_rc_buckets);
 size_t lds_rc_bytes(uint32_t slots_log2);
-size_t lds_links_wave_bytes(uint32_t hist);
+size_t lds_links_wave_bytes(uint32_t hist, uint32_t rows);
 hipError_t allow_large_lds(size_t bytes);
 hipError_t resident_blocks(int which, uint32_t tile_log2, size_t lds, int* blocks);
 }  // namespace nsgc
@@ -199,10 +201,11 @@ inline int wave_class(uint32_t rc_max) { return rc_max <= 64 ? 0 : 1; }
 
 struct Launch {
   uint32_t grid_small, grid_part, grid_link, grid_rc, grid_finish, grid_rce;  // persistent grids
-  uint32_t grid_linkw[2];                              // per wave_class
+  uint32_t grid_linkw[2][2];                           // per wave_class, row tables
+  uint32_t grid_heavy;
   bool combine;                                        // phase-B emission combines per id
   size_t lds_small, lds_part, lds_link, lds_rc, lds_rce;
-  size_t lds_linkw[2];
+  size_t lds_linkw[2][2];
   uint32_t max_link_buckets, max_rc_buckets;
 };
 
@@ -231,9 +234,10 @@ int launch_params(DevCtx* c, const nsgc_tune& t, Launch* out) {
   L.lds_part = lds_part_bytes(L.max_link_buckets, tile, L.max_rc_buckets);
   L.lds_link = lds_link_bytes(uint32_t(t.link_slots_log2), L.max_rc_buckets);
   L.lds_rc = lds_rc_bytes(uint32_t(t.rc_slots_log2));
-  for (int k = 0; k < 2; ++k) L.lds_linkw[k] = lds_links_wave_bytes(kWaveHist[k]);
+  for (int k = 0; k < 2; ++k)
+    for (int r = 0; r < 2; ++r) L.lds_linkw[k][r] = lds_links_wave_bytes(kWaveHist[k], uint32_t(r));
   const size_t m = std::max(std::max(std::max(L.lds_small, L.lds_part), std::max(L.lds_link, L.lds_rc)),
-                            L.lds_linkw[1]);
+                            std::max(L.lds_linkw[1][1], lds_heavy_bytes()));
   if (m > c->lds_limit) return NSGC_ERR_INVALID_ARG;
   int rc;
   const int want = t.blocks_per_cu;
@@ -246,9 +250,12 @@ int launch_params(DevCtx* c, const nsgc_tune& t, Launch* out) {
   // the wavefront kernel runs four small workgroups per CU for every one of
   // the workgroup kernels' 512-thread workgroups
   for (int k = 0; k < 2; ++k)
-    if ((rc = resident_cap(c, 5, tile, L.lds_linkw[k], 4 * want, &L.grid_linkw[k])) != NSGC_OK)
-      return rc;
+    for (int r = 0; r < 2; ++r)
+      if ((rc = resident_cap(c, 5, tile, L.lds_linkw[k][r], 4 * want, &L.grid_linkw[k][r])) !=
+          NSGC_OK)
+        return rc;
   L.grid_finish = uint32_t(c->cus) * 4;
+  L.grid_heavy = uint32_t(c->cus);   // one workgroup per row-complete window
   // the entity outputs' phase C (two tables per workgroup)
   L.lds_rce = lds_rc_ent_bytes(uint32_t(std::min(t.rc_slots_log2, 12)));
   L.grid_rce = 0;
@@ -261,11 +268,13 @@ int launch_params(DevCtx* c, const nsgc_tune& t, Launch* out) {
 
 // Which kernels a plan needs: bit 0 the small-window kernel, bit 1 phases A
 // and C, bit 2 phase B by workgroups, bit 3 phase B by wavefronts, bit 4 the
-// wavefront kernel's larger counters (see wave_class).
-constexpr int kVariants = 32;
+// wavefront kernel's larger counters (see wave_class), bit 5 row-complete
+// windows (the heavy-source sample and the wavefront kernel's row tables).
+constexpr int kVariants = 64;
 int plan_variant(const HostPlan& hp) {
   return (hp.small.empty() ? 0 : 1) | (hp.win.empty() ? 0 : 2) | (hp.itemsBb ? 4 : 0) |
-         (hp.itemsBw ? 8 : 0) | (hp.itemsBw && wave_class(hp.wave_rc_max) ? 16 : 0);
+         (hp.itemsBw ? 8 : 0) | (hp.itemsBw && wave_class(hp.wave_rc_max) ? 16 : 0) |
+         (hp.num_rows ? 32 : 0);
 }
 
 // Enqueue the kernels of one uploaded plan.  With `fixed_grid` (graph
@@ -290,18 +299,22 @@ int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch
   const bool part = fixed_grid ? (variant & 2) != 0 : !hp.win.empty();
   const bool linkb = fixed_grid ? (variant & 4) != 0 : hp.itemsBb > 0;
   const bool linkw = fixed_grid ? (variant & 8) != 0 : hp.itemsBw > 0;
+  const bool rows = fixed_grid ? (variant & 32) != 0 : hp.num_rows > 0;
   NSGC_HIP(mark(0));
   if (small)
     NSGC_HIP(launch_small(dplan, grid(uint32_t(hp.small.size()), L.grid_small), L.lds_small, s));
   NSGC_HIP(mark(1));
+  if (rows) NSGC_HIP(launch_heavy(dplan, grid(uint32_t(hp.win.size()), L.grid_heavy), s));
   if (part)
     NSGC_HIP(launch_partition(dplan, tile_log2, L.max_link_buckets, grid(hp.itemsA, L.grid_part),
                               L.lds_part, s));
   NSGC_HIP(mark(2));
   if (linkw) {
     const int wc = fixed_grid ? ((variant & 16) ? 1 : 0) : wave_class(hp.wave_rc_max);
-    NSGC_HIP(launch_links_wave(dplan, kWaveHist[wc], grid((hp.itemsBw + 3) / 4, L.grid_linkw[wc]),
-                               L.lds_linkw[wc], s));
+    const int r = rows ? 1 : 0;
+    NSGC_HIP(launch_links_wave(dplan, kWaveHist[wc], uint32_t(r),
+                               grid((hp.itemsBw + 3) / 4, L.grid_linkw[wc][r]), L.lds_linkw[wc][r],
+                               s));
   }
   if (linkb)
     NSGC_HIP(launch_links(dplan, L.combine && !hp.entity, L.max_rc_buckets,
@@ -397,6 +410,8 @@ size_t workspace_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune
   // bucket totals: 16 B per phase-B and per phase-C item
   const uint64_t bitems = std::min<uint64_t>(2 * P / uint64_t(lt) + 2 * W, W * MB);
   size_t b = size_t(P * 24 + (tilemeta + lbmeta + 2 * items) * 4 + (bitems + items) * 16 + 10 * 256);
+  // row-complete windows: source totals per phase-B item and a heavy table per window
+  if (t.row_complete) b += size_t(bitems * 16 + W * NSGC_HEAVY_SLOTS * 4 + 2 * 256);
   // a large window's region comes on top of the partitioned windows' regions
   if (large && t.large_min_log2 < 33 && P >= (uint64_t(1) << t.large_min_log2))
     b += large_window_bytes(P) + 256;

@@ -366,6 +366,106 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
 }
 
 // ---------------------------------------------------------------------------
+// Heavy sources of the row-complete windows.
+//
+// One workgroup per window counts the hashed sources of a sample of
+// NSGC_HEAVY_SAMPLE packets: sixteen runs of 256 consecutive packets spread
+// evenly from the window's first packet to its last (all packets of a smaller
+// window).  A source is heavy when its sample count puts it above half a link
+// bucket's share of the packets.  The window's table holds them in sets of
+// four, the set chosen by the id's low bits; a set keeps its four most
+// frequent candidates (a dropped one would fill its home bucket alone), and
+// an unused slot holds a value whose low bits name another set, so it matches
+// no id.  Which sources the table names decides only how evenly the buckets
+// fill: the partition and phase B read the same table, and every result is
+// exact for any table.
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t HEAVY_SETS = NSGC_HEAVY_SLOTS / 4;
+constexpr uint32_t HEAVY_TABLE = 2 * NSGC_HEAVY_SAMPLE;   // sample counting table
+constexpr uint32_t HEAVY_CAND = NSGC_HEAVY_SAMPLE / 2;    // counts >= 2: at most m / 2 candidates
+static_assert(NSGC_HEAVY_SAMPLE == 16 * 256, "sixteen runs of 256 packets");
+static_assert(HEAVY_SETS <= NSGC_BLOCK, "one thread per set");
+
+size_t lds_heavy_bytes() { return size_t(HEAVY_TABLE) * 8 + size_t(HEAVY_CAND) * 8 + 16; }
+
+__global__ __launch_bounds__(NSGC_BLOCK) void k_heavy(const nsgc_dev_plan* __restrict__ P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  u64* cand = reinterpret_cast<u64*>(smem);               // [HEAVY_CAND] count << 32 | id
+  uint32_t* key = reinterpret_cast<uint32_t*>(cand + HEAVY_CAND);   // [HEAVY_TABLE]
+  uint32_t* cnt = key + HEAVY_TABLE;                      // [HEAVY_TABLE]
+  uint32_t* ncand = cnt + HEAVY_TABLE;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t wi = blockIdx.x; wi < P->num_part; wi += gridDim.x) {
+    const nsgc_win_desc W = gload(P->win + wi);
+    if (!W.rows) continue;   // the same for the whole workgroup
+    for (uint32_t i = tid; i < HEAVY_TABLE; i += NSGC_BLOCK) {
+      key[i] = EMPTY32;
+      cnt[i] = 0;
+    }
+    if (tid == 0) *ncand = 0;
+    __syncthreads();
+    const uint32_t m = min(W.n, NSGC_HEAVY_SAMPLE);
+    const NSGC_GLOBAL uint32_t* src = gptr(P->src) + W.in_begin;
+    for (uint32_t i = tid; i < m; i += NSGC_BLOCK) {
+      const uint32_t at = W.n <= NSGC_HEAVY_SAMPLE
+                              ? i
+                              : uint32_t(u64(W.n - 256u) * (i >> 8) / 15u) + (i & 255u);
+      const uint32_t r = row_hash(src[at]);
+      if (r == EMPTY32) continue;   // this id keeps per-link entries anyway
+      bool fresh;
+      const int sl = lds_insert32(key, HEAVY_TABLE - 1, r, r, fresh);   // never full: 2x the sample
+      if (sl >= 0) lds_add(&cnt[sl], 1);
+    }
+    __syncthreads();
+    // estimated packets cnt * n / m above n / (2 B): cnt > m / (2 B)
+    const uint32_t thr = max(2u, (m >> (W.logB + 1)) + 1u);
+    for (uint32_t i = tid; i < HEAVY_TABLE; i += NSGC_BLOCK) {
+      const uint32_t c = cnt[i];
+      if (c >= thr) cand[lds_add(ncand, 1)] = (u64(c) << 32) | key[i];
+    }
+    __syncthreads();
+    // thread j keeps set j's four largest (count, id) candidates
+    const uint32_t nc = *ncand;
+    NSGC_GLOBAL uint32_t* out = gptr(P->heavy) + u64(W.counter) * NSGC_HEAVY_SLOTS;
+    if (tid < HEAVY_SETS) {
+      u64 top[4] = {0, 0, 0, 0};
+      for (uint32_t i = 0; i < nc; ++i) {
+        u64 v = cand[i];
+        if ((uint32_t(v) & (HEAVY_SETS - 1)) != tid) continue;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (v > top[k]) {
+            const u64 t = top[k];
+            top[k] = v;
+            v = t;
+          }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) out[tid * 4 + k] = top[k] ? uint32_t(top[k]) : ~tid;
+    }
+    __syncthreads();
+  }
+}
+
+// Whether hashed source r is in a window's heavy table (LDS, 16-byte aligned).
+__device__ __forceinline__ bool heavy_source(const uint32_t* hv, uint32_t r) {
+  const v4u32 q = *reinterpret_cast<const v4u32*>(hv + (r & (HEAVY_SETS - 1)) * 4);
+  return q.x == r || q.y == r || q.z == r || q.w == r;
+}
+
+// Link bucket of key k in a row-complete window of 2^logB >= 2 buckets: a
+// light source's links all go to its home bucket, the top bits of its hashed
+// id; a heavy source's links go to the other 2^logB - 1 buckets, home ^ x with
+// x in 1 .. 2^logB - 1 from the destination hash, so they never meet the home.
+__device__ __forceinline__ uint32_t row_bucket(u64 k, uint32_t logB, bool heavy) {
+  const uint32_t r = uint32_t(k >> 32), c = uint32_t(k);
+  const uint32_t home = top32(r, logB);
+  const uint32_t x = 1u + uint32_t((u64(c) * ((1u << logB) - 1u)) >> 32);
+  return heavy ? home ^ x : home;
+}
+
+// ---------------------------------------------------------------------------
 // Phase A: partition a tile of packets by link bucket.
 //
 // Each thread holds PER packets in registers (16-byte loads when the tile is
@@ -378,7 +478,8 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_small(nsgc_dev_plan* P) {
 
 size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2, uint32_t max_rc_buckets) {
   (void)max_rc_buckets;   // the row/column sample shares the staging area
-  return align16((max_link_buckets + 1) * 4) + align16((size_t(1) << tile_log2) * 8) + 256;
+  return align16((max_link_buckets + 1) * 4) + align16((size_t(1) << tile_log2) * 8) + 256 +
+         NSGC_HEAVY_SLOTS * 4;
 }
 
 template <int PER, int NT = NSGC_BLOCK>
@@ -390,6 +491,7 @@ __global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restric
   uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
   u64* stage = reinterpret_cast<u64*>(smem + align16((max_link_buckets + 1) * 4));
   uint32_t* red = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(stage) + T * 8);
+  uint32_t* hv = red + 64;   // the window's heavy sources (row-complete windows)
   // packets per row and column bucket of a window's first tile; in the staging
   // area, which is free until the bucket scan's barriers
   uint32_t* rch = reinterpret_cast<uint32_t*>(stage);
@@ -413,6 +515,10 @@ __global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restric
     for (uint32_t i = threadIdx.x; i < B; i += NT) hist[i] = 0;
     if (sample)
       for (uint32_t i = threadIdx.x; i < R + C; i += NT) rch[i] = 0;
+    const bool rows = W.rows != 0;
+    if (rows)
+      for (uint32_t i = threadIdx.x; i < NSGC_HEAVY_SLOTS; i += NT)
+        hv[i] = gptr(P->heavy)[u64(W.counter) * NSGC_HEAVY_SLOTS + i];
     __syncthreads();
 
     const uint64_t gbeg = uint64_t(W.in_begin) + tbeg;
@@ -451,18 +557,23 @@ __global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restric
 #pragma unroll
       for (int k = 0; k < PER; ++k) key[k] = link_key(sv[k], dv[k], same);
     }
+    bool hvy[PER];   // row-complete windows: the packet's source is heavy
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
+      hvy[k] = rows && heavy_source(hv, uint32_t(key[k] >> 32));
       if (ok[k]) {
-        const uint32_t bk = top64(link_pos(key[k]), W.logB);
+        const uint32_t bk =
+            rows ? row_bucket(key[k], W.logB, hvy[k]) : top64(link_pos(key[k]), W.logB);
         br[k] = (lds_add(&hist[bk], 1) << 12) | bk;
       }
     }
     if (sample) {
+      // a light source of a row-complete window sends nothing to phase C
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
         if (ok[k]) {
-          lds_add(&rch[top32(uint32_t(key[k] >> 32), W.logR)], 1);
+          const uint32_t r = uint32_t(key[k] >> 32);
+          if (!rows || hvy[k] || r == EMPTY32) lds_add(&rch[top32(r, W.logR)], 1);
           lds_add(&rch[R + top32(uint32_t(key[k]), W.logC)], 1);
         }
       }
@@ -1203,17 +1314,22 @@ constexpr uint32_t WAVE_SLOTS = 1u << NSGC_WAVE_SLOTS_LOG2;
 
 static_assert(WAVE_SLOTS <= 65536, "slots are listed as 16-bit indices");
 
+constexpr uint32_t WAVE_ROWS = NSGC_WAVE_ROW_SLOTS;
+
 // LDS of one wavefront: keys, counts, the row and column bucket counters
 // (`hist` per view: one more than the launch's largest row or column bucket
-// count, so that batches of small windows fit more wavefronts per CU) and the
-// occupied-slot list.
-__host__ __device__ constexpr size_t wave_lds_stride(uint32_t hist) {
+// count, so that batches of small windows fit more wavefronts per CU), the
+// occupied-slot list and, in launches with row-complete windows, the row
+// table (hashed source id, links << 20 | packets).
+__host__ __device__ constexpr size_t wave_lds_stride(uint32_t hist, uint32_t rows) {
   return (size_t(WAVE_SLOTS) * 8 + size_t(WAVE_SLOTS) * 4 + 2 * size_t(hist) * 4 +
-          size_t(WAVE_SLOTS) * 2 + 15) &
+          size_t(WAVE_SLOTS) * 2 + (rows ? size_t(WAVE_ROWS) * 8 : 0) + 15) &
          ~size_t(15);
 }
 
-size_t lds_links_wave_bytes(uint32_t hist) { return size_t(WAVE_WPB) * wave_lds_stride(hist); }
+size_t lds_links_wave_bytes(uint32_t hist, uint32_t rows) {
+  return size_t(WAVE_WPB) * wave_lds_stride(hist, rows);
+}
 
 __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1277,21 +1393,29 @@ struct WaveQueue {
   }
 };
 
-__global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32_t hist) {
+__global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32_t hist,
+                                                        uint32_t rows) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t w = uniform(threadIdx.x >> 6), lane = lane_id();
-  unsigned char* p = smem + size_t(w) * wave_lds_stride(hist);
+  unsigned char* p = smem + size_t(w) * wave_lds_stride(hist, rows);
   u64* tk = reinterpret_cast<u64*>(p);             p += size_t(WAVE_SLOTS) * 8;
   uint32_t* tc = reinterpret_cast<uint32_t*>(p);   p += size_t(WAVE_SLOTS) * 4;
   uint32_t* histR = reinterpret_cast<uint32_t*>(p);  p += size_t(hist) * 4;
   uint32_t* histC = reinterpret_cast<uint32_t*>(p);  p += size_t(hist) * 4;
-  uint16_t* occ = reinterpret_cast<uint16_t*>(p);
+  uint16_t* occ = reinterpret_cast<uint16_t*>(p);    p += size_t(WAVE_SLOTS) * 2;
+  uint32_t* rk = reinterpret_cast<uint32_t*>(p);     p += size_t(WAVE_ROWS) * 4;   // if rows
+  uint32_t* rv = reinterpret_cast<uint32_t*>(p);
   constexpr uint32_t S = WAVE_SLOTS;
 
   for (uint32_t i = lane; i < S; i += 64) {
     tk[i] = EMPTY64;
     tc[i] = 0;
   }
+  if (rows)
+    for (uint32_t i = lane; i < WAVE_ROWS; i += 64) {
+      rk[i] = EMPTY32;
+      rv[i] = 0;
+    }
   wave_fence();
 
   const uint32_t T = 1u << P->tile_log2;
@@ -1323,12 +1447,21 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
     uint32_t n = 0;        // occupied slots (uniform)
     uint32_t special = 0;  // packets of the key equal to the empty marker (uniform)
     uint32_t links = 0, sum = 0, mx = 0;   // the bucket's statistics
+    uint32_t pk = 0;       // the bucket's packets (uniform)
+    // Row-complete window, single table: the bucket's links are combined per
+    // source in the row table; sources at home here are complete (their
+    // totals go to partR), the others leave one entry each.  Per-link row
+    // entries otherwise, and always for the id EMPTY32 (the table's marker).
+    const bool rowc = rows && W.rows;
+    bool local = false;
+    uint32_t nrows = 0, rmaxp = 0, rmaxl = 0;   // complete sources: count and maxima
 
     // Link table of sweep `sw` of 2^logS; false if an insert gave up (after
     // `probes` probes).
     auto build = [&](uint32_t logS, uint32_t sw, uint32_t probes) -> bool {
       n = 0;
       special = 0;
+      pk = 0;
       bool gave_up = false;
       for (uint32_t g0 = 0; g0 < nt; g0 += 64) {
         const uint32_t t = g0 + lane;
@@ -1342,6 +1475,7 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
         // walk the concatenation of the group's segments, 64 keys per chunk
         const uint32_t incl = wave_inclusive_scan(len);
         const uint32_t elems = uniform(readlane(incl, 63));
+        pk += elems;
         const uint32_t start = incl - len;      // exclusive prefix: the segment's first element
         const u64 nonempty = __ballot(len > 0);
         mb -= start;                            // base minus exclusive prefix
@@ -1446,7 +1580,8 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
         mx = max(mx, c);
         const u64 key = tk[s];
         const uint32_t parts = entry_parts(c, 1);
-        lds_add(&histR[top32(uint32_t(key >> 32), W.logR)], parts);
+        const uint32_t r = uint32_t(key >> 32);
+        if (!local || r == EMPTY32) lds_add(&histR[top32(r, W.logR)], parts);
         lds_add(&histC[top32(uint32_t(key), W.logC)], parts);
       }
       links += n + (special ? 1u : 0u);
@@ -1457,7 +1592,59 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
         lds_add(&histR[top32(EMPTY32, W.logR)], parts);
         lds_add(&histC[top32(EMPTY32, W.logC)], parts);
       }
+      if (local) {
+        // sources at home in bucket b are complete; the others leave an entry
+        for (uint32_t i = lane; i < WAVE_ROWS; i += 64) {
+          const uint32_t r = rk[i];
+          if (r == EMPTY32) continue;
+          const uint32_t v = rv[i], np = v & 0xFFFFFu, nl = v >> 20;
+          if (top32(r, W.logB) == b) {
+            ++nrows;
+            rmaxp = max(rmaxp, np);
+            rmaxl = max(rmaxl, nl);
+          } else {
+            lds_add(&histR[top32(r, W.logR)], entry_parts(np, nl));
+          }
+        }
+      }
       wave_fence();
+    };
+
+    // The table's links per source into the row table (packets < 2^20 per
+    // bucket, so links << 20 | packets cannot carry).  False, with the row
+    // table emptied, if a source finds no slot within NSGC_MAX_PROBES probes.
+    auto rows_build = [&]() -> bool {
+      bool failed = false;
+      for (uint32_t i0 = 0; i0 < n; i0 += 64) {
+        const uint32_t i = i0 + lane;
+        if (i < n) {
+          const uint32_t s = occ[i];
+          const uint32_t r = uint32_t(tk[s] >> 32);
+          if (r != EMPTY32) {
+            uint32_t at = r & (WAVE_ROWS - 1);
+            int got = -1;
+            for (uint32_t q = 0; q < NSGC_MAX_PROBES; ++q) {
+              const uint32_t o = lds_cas32(&rk[at], EMPTY32, r);
+              if (o == EMPTY32 || o == r) {
+                got = int(at);
+                break;
+              }
+              at = (at + 1) & (WAVE_ROWS - 1);
+            }
+            if (got >= 0) lds_add(&rv[got], (1u << 20) | tc[s]);
+            else failed = true;
+          }
+        }
+        if (__ballot(failed)) break;
+      }
+      const bool bad = __ballot(failed) != 0;
+      if (bad)
+        for (uint32_t i = lane; i < WAVE_ROWS; i += 64) {
+          rk[i] = EMPTY32;
+          rv[i] = 0;
+        }
+      wave_fence();
+      return !bad;
     };
 
     // counts -> starts, published for phase C (and the phase-C sizes)
@@ -1479,9 +1666,12 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
         tk[s] = EMPTY64;
         tc[s] = 0;
         const uint32_t parts = entry_parts(cnt, 1);
-        const uint32_t ar = lds_add(&histR[top32(uint32_t(key >> 32), W.logR)], parts);
+        const uint32_t r = uint32_t(key >> 32);
+        if (!local || r == EMPTY32) {
+          const uint32_t ar = lds_add(&histR[top32(r, W.logR)], parts);
+          write_entry(er, ar, r, cnt, 1, parts);
+        }
         const uint32_t ac = lds_add(&histC[top32(uint32_t(key), W.logC)], parts);
-        write_entry(er, ar, uint32_t(key >> 32), cnt, 1, parts);
         write_entry(ec, ac, uint32_t(key), cnt, 1, parts);
         if (P->ent_links) {   // entity outputs: the links themselves
           const u64 row = ent_reserve(P, W.out_index, 0, true);
@@ -1500,6 +1690,19 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
         write_entry(er, lds_add(&histR[top32(EMPTY32, W.logR)], parts), EMPTY32, special, 1, parts);
         write_entry(ec, lds_add(&histC[top32(EMPTY32, W.logC)], parts), EMPTY32, special, 1, parts);
       }
+      if (local) {   // one entry per source away from home; empties the row table
+        for (uint32_t i = lane; i < WAVE_ROWS; i += 64) {
+          const uint32_t r = rk[i];
+          if (r == EMPTY32) continue;
+          const uint32_t v = rv[i];
+          rk[i] = EMPTY32;
+          rv[i] = 0;
+          if (top32(r, W.logB) != b) {
+            const uint32_t np = v & 0xFFFFFu, nl = v >> 20, parts = entry_parts(np, nl);
+            write_entry(er, lds_add(&histR[top32(r, W.logR)], parts), r, np, nl, parts);
+          }
+        }
+      }
       n = 0;
       wave_fence();
     };
@@ -1508,6 +1711,8 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
     for (uint32_t logS = 0;; ++logS) {
       if (logS > P->max_sweeps_log2) { abandoned = true; break; }
       links = sum = mx = 0;
+      nrows = rmaxp = rmaxl = 0;
+      local = false;
       for (uint32_t i = lane; i <= R; i += 64) histR[i] = 0;
       for (uint32_t i = lane; i <= C; i += 64) histC[i] = 0;
       wave_fence();
@@ -1520,6 +1725,7 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
           // whole table (chains depend on the order of concurrent inserts)
           if (!build(logS, sw, pass ? S : NSGC_MAX_PROBES)) { failed = true; reset(); break; }
           if (pass == 1) { emit(); continue; }
+          if (logS == 0) local = rowc && pk < (1u << 20) && rows_build();
           count();
           if (logS == 0) {
             publish();
@@ -1541,6 +1747,15 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
     if (lane == 0) {   // the bucket's totals, combined per window by k_finish
       const v4u32 part = {sum, links, mx, abandoned ? 1u : 0u};
       gptr(reinterpret_cast<v4u32*>(P->partB))[it] = part;
+    }
+    if (rowc) {   // the bucket's complete sources
+      nrows = wave_sum(nrows);
+      rmaxp = wave_max(rmaxp);
+      rmaxl = wave_max(rmaxl);
+      if (lane == 0) {
+        const v4u32 part = {nrows, rmaxp, rmaxl, 0u};
+        gptr(reinterpret_cast<v4u32*>(P->partR))[it] = part;
+      }
     }
   }
 }
@@ -2067,6 +2282,16 @@ __global__ __launch_bounds__(256) void k_finish(nsgc_dev_plan* P) {
       v[4] = max(v[4], x.z);
       v[9] |= x.w;
     }
+    if (W.rows) {   // sources complete in their home link bucket
+      const NSGC_GLOBAL v4u32* pr =
+          gptr(reinterpret_cast<const v4u32*>(P->partR)) + gptr(P->prefB)[wi];
+      for (uint32_t i = tid; i < B; i += 256) {
+        const v4u32 x = pr[i];
+        v[2] += x.x;
+        v[5] = max(v[5], x.y);
+        v[6] = max(v[6], x.z);
+      }
+    }
     for (uint32_t i = tid; i < R + C; i += 256) {
       const v4u32 x = pc[i];
       const bool row = i < R;
@@ -2153,10 +2378,15 @@ hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_bu
   return hipGetLastError();
 }
 
-hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t hist, uint32_t grid, size_t lds,
-                             hipStream_t s) {
+hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t hist, uint32_t rows, uint32_t grid,
+                             size_t lds, hipStream_t s) {
   hipLaunchKernelGGL(k_links_wave, dim3(grid), dim3(WAVE_NT), lds, s, const_cast<nsgc_dev_plan*>(P),
-                     hist);
+                     hist, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_heavy(const nsgc_dev_plan* P, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_heavy, dim3(grid), dim3(NSGC_BLOCK), lds_heavy_bytes(), s, P);
   return hipGetLastError();
 }
 
@@ -2211,7 +2441,7 @@ hipError_t allow_large_lds(size_t bytes) {
   const void* fns[] = {
       reinterpret_cast<const void*>(&k_small),         reinterpret_cast<const void*>(&k_links<false>),
       reinterpret_cast<const void*>(&k_links<true>),   reinterpret_cast<const void*>(&k_links_wave),
-      reinterpret_cast<const void*>(&k_rowcol_ent),
+      reinterpret_cast<const void*>(&k_rowcol_ent),    reinterpret_cast<const void*>(&k_heavy),
       reinterpret_cast<const void*>(&k_rowcol),        reinterpret_cast<const void*>(&k_partition<4>),
       reinterpret_cast<const void*>(&k_partition<8>),  reinterpret_cast<const void*>(&k_partition<16>),
       reinterpret_cast<const void*>(&k_partition<32 / PART14_SCALE, NSGC_BLOCK * PART14_SCALE>)};

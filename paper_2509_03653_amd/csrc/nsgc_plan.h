@@ -30,6 +30,15 @@
 //   Every phase-B and phase-C item stores its bucket's totals (counts and
 //   maxima); k_finish combines them per window by sums and maxima, which is
 //   exact because buckets partition the links, sources and destinations.
+//   Row-complete windows: before A, a sample of each window's sources marks
+//   the heavy ones (table `heavy`).  A puts every link of a light source s
+//   in bucket top(row_hash(s)) and spreads a heavy source's links over the
+//   other buckets, top(row_hash(s)) ^ x with x in 1..B-1 from the
+//   destination hash.  So a source met in bucket b with top(row_hash) == b
+//   has all its links there: B combines the bucket's links per source and
+//   stores the totals of those sources (partR); every other source leaves one
+//   entry (packets, links) per bucket for C.  The id EMPTY32 and buckets
+//   that sweep keep per-link row entries.
 #ifndef NSGC_PLAN_H_
 #define NSGC_PLAN_H_
 
@@ -55,6 +64,13 @@
 // wavefront, and the most row (or column) buckets such a window may have.
 #define NSGC_WAVE_SLOTS_LOG2 9
 #define NSGC_WAVE_MAX_RC 256
+// Row-complete windows (tune row_complete): slots of a window's table of
+// heavy sources (sets of four ids, the set picked by the hashed id's low
+// bits), the sample of packets it is drawn from, and the LDS row table of
+// each phase-B wavefront.
+#define NSGC_HEAVY_SLOTS 512
+#define NSGC_HEAVY_SAMPLE 4096
+#define NSGC_WAVE_ROW_SLOTS 256
 
 struct nsgc_small_desc {        // 16 bytes
   int64_t in_begin;             // index of the window's first packet
@@ -73,7 +89,9 @@ struct nsgc_win_desc {          // 64 bytes
   uint32_t counter;             // index of the window among partitioned windows
   uint8_t logB, logR, logC;
   uint8_t wave;                 // 1: phase B runs one wavefront per link bucket
-  uint32_t pad1[3];
+  uint8_t rows;                 // 1: row-complete (wavefront windows only, logB >= 1)
+  uint8_t pad0[3];
+  uint32_t pad1[2];
 };
 
 // Tile bucket starts, bucket-major: word b * ntiles + t holds the number of
@@ -136,6 +154,10 @@ struct nsgc_dev_plan {          // header of the device plan buffer
   const unsigned long long* ent_end;  // [windows][3] end of each window's rows
   long long* ent_counts;        // [windows][4] nsgc_entity_counts
   uint32_t* partU;              // [itemsC] union count of each merged phase-C item
+  // Row-complete windows (null when the batch has none).
+  uint32_t* heavy;              // [num_part][NSGC_HEAVY_SLOTS] heavy sources, 4-way sets
+  uint32_t* partR;              // [itemsB][4] complete sources of a bucket: count, max packets,
+                                //   max links, 0
   // Work-queue counters of the small, B (workgroup), C and B (wavefront)
   // kernels.  Uploaded as zero with every plan.
   uint32_t queue[4][NSGC_QCLASSES * NSGC_QSTRIDE];

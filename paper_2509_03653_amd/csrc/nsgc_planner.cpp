@@ -32,6 +32,7 @@ void default_tune(nsgc_tune* t) {
   t->max_sweeps_log2 = 24;
   t->combine_probes = 0;
   t->large_min_log2 = 24;
+  t->row_complete = 0;
   // Per size class (windows of [2^k, 2^(k+1)) packets): below 2^23 packets a
   // link bucket holds at most as many packets as its LDS table has slots (at
   // 2^23, twice as many), so it sweeps only when nearly all its packets are
@@ -62,6 +63,7 @@ int check_tune(const nsgc_tune& t) {
   if (t.max_sweeps_log2 < 0 || t.max_sweeps_log2 > 24) return NSGC_ERR_INVALID_ARG;
   if (t.combine_probes < 0 || t.combine_probes > 64) return NSGC_ERR_INVALID_ARG;
   if (t.large_min_log2 < 20 || t.large_min_log2 > 33) return NSGC_ERR_INVALID_ARG;
+  if (t.row_complete < 0 || t.row_complete > 1) return NSGC_ERR_INVALID_ARG;
   for (int k = 0; k <= 32; ++k) {
     const nsgc_tune_class& c = t.cls[k];
     if (c.link_target < 64 || c.row_target < 64 || c.col_target < 64) return NSGC_ERR_INVALID_ARG;
@@ -98,6 +100,7 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
   p->mapBw.clear();
   p->itemsBb = p->itemsBw = 0;
   p->wave_rc_max = 0;
+  p->num_rows = 0;
   p->tier.assign(size_t(num_windows), 0);
   p->ws_elems = p->tilemeta_words = p->lbmeta_words = 0;
   p->tile_log2 = uint32_t(tune.tile_log2);
@@ -150,6 +153,11 @@ int make_plan(const int64_t* offsets, int64_t num_windows, const nsgc_tune& tune
         p->wave_rc_max = std::max(p->wave_rc_max, 1u << std::max(d.logR, d.logC));
       }
     }
+    // row-complete: wavefront windows of two or more link buckets
+    if (tune.row_complete && d.wave && !entity && d.logB >= 1) {
+      d.rows = 1;
+      ++p->num_rows;
+    }
     d.ntiles = uint32_t((n + tile - 1) / tile);
     d.counter = uint32_t(p->win.size());
     d.ws = p->ws_elems;
@@ -200,6 +208,10 @@ WsLayout HostPlan::layout() const {
   L.order = o;     o = align_up(o + size_t(itemsC) * 4, 256);
   L.partB = o;     o = align_up(o + size_t(itemsB) * 16, 256);
   L.partC = o;     o = align_up(o + size_t(itemsC) * 16, 256);
+  if (num_rows) {
+    L.partR = o;   o = align_up(o + size_t(itemsB) * 16, 256);
+    L.heavy = o;   o = align_up(o + win.size() * NSGC_HEAVY_SLOTS * 4, 256);
+  }
   if (entity) {
     L.partU = o;   o = align_up(o + size_t(itemsC) * 4, 256);
     L.stats = o;   o = align_up(o + tier.size() * 72, 256);
@@ -287,6 +299,10 @@ void HostPlan::serialize(void* buf, uint64_t dev_plan, uint64_t dev_ws, const ui
   h.order = reinterpret_cast<uint32_t*>(dev_ws + L.order);
   h.partB = reinterpret_cast<uint32_t*>(dev_ws + L.partB);
   h.partC = reinterpret_cast<uint32_t*>(dev_ws + L.partC);
+  if (num_rows) {
+    h.partR = reinterpret_cast<uint32_t*>(dev_ws + L.partR);
+    h.heavy = reinterpret_cast<uint32_t*>(dev_ws + L.heavy);
+  }
   h.small = reinterpret_cast<const nsgc_small_desc*>(dev_plan + o.small);
   h.win = reinterpret_cast<const nsgc_win_desc*>(dev_plan + o.win);
   h.prefA = reinterpret_cast<const uint32_t*>(dev_plan + o.prefA);

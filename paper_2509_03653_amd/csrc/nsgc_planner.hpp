@@ -16,7 +16,7 @@ namespace nsgc {
 // Workspace regions of one batch, as byte offsets from the workspace base.
 struct WsLayout {
   size_t keys = 0, emit_row = 0, emit_col = 0, tilemeta = 0, lbmeta = 0, rcsize = 0, order = 0,
-         partB = 0, partC = 0, partU = 0, stats = 0, large = 0;
+         partB = 0, partC = 0, partU = 0, stats = 0, large = 0, partR = 0, heavy = 0;
   size_t total = 0;
 };
 
@@ -37,6 +37,7 @@ struct HostPlan {
   std::vector<uint32_t> mapBb, mapBw;         // phase-B items by kernel (empty: identity)
   uint32_t itemsBb = 0, itemsBw = 0;
   uint32_t wave_rc_max = 0;    // largest row or column bucket count of a wavefront window
+  uint32_t num_rows = 0;       // row-complete windows (tune row_complete)
   int64_t ws_elems = 0;        // packets of the partitioned windows
   int64_t tilemeta_words = 0;  // u32 words of tile bucket starts
   int64_t lbmeta_words = 0;    // u32 words of link-bucket records

@@ -91,7 +91,8 @@ def test_tune_roundtrip_and_validation():
                  ("rc_slots_log2", 14), ("small_max", 2049), ("blocks_per_cu", 0),
                  ("max_link_buckets_log2", 13), ("max_rc_buckets_log2", 13),
                  ("max_link_buckets_log2", -1), ("max_sweeps_log2", 25), ("max_sweeps_log2", -1),
-                 ("combine_probes", -1), ("combine_probes", 65)):
+                 ("combine_probes", -1), ("combine_probes", 65), ("row_complete", 2),
+                 ("row_complete", -1)):
         with pytest.raises(nsgc.NsgcError):
             nsgc.set_tune(nsgc.Tune.from_dict(dict(d, **{k: v})))
         assert nsgc.get_tune().to_dict() == d, k
@@ -170,6 +171,30 @@ def test_default_buckets_sized_by_their_tables():
         assert -(-n // (1 << lc)) <= rc_room, (n, lc)
 
 
+def test_row_complete_plans_the_same_buckets_with_more_workspace():
+    # row_complete changes how packets are spread over the link buckets, not
+    # how many there are; its per-bucket source totals and per-window heavy
+    # tables add workspace only when a wavefront window is present
+    sizes = [500, 3000, 1 << 17, 1 << 21]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    before = nsgc.get_tune()
+    try:
+        nsgc.set_tune(nsgc.default_tune())
+        q = nsgc.plan_inspect(off)
+        base = nsgc.default_tune().to_dict()
+        base["row_complete"] = 1
+        nsgc.set_tune(nsgc.Tune.from_dict(base))
+        p = nsgc.plan_inspect(off)
+        for k in ("tier", "log2_link_buckets", "log2_row_buckets", "log2_col_buckets", "tiles"):
+            assert (p[k] == q[k]).all(), k
+        assert p["workspace_bytes"] > q["workspace_bytes"]
+        big = np.array([0, 1 << 21], np.int64)   # workgroup windows only: nothing added
+        assert nsgc.plan_inspect(big)["workspace_bytes"] == (
+            nsgc.set_tune(nsgc.default_tune()) or nsgc.plan_inspect(big)["workspace_bytes"])
+    finally:
+        nsgc.set_tune(before)
+
+
 def test_plan_rejects_bad_offsets():
     with pytest.raises(nsgc.NsgcError):
         nsgc.plan_inspect(np.array([0, 5, 2], np.int64))
@@ -197,6 +222,8 @@ def test_no_cpu_path():
     {"tile_log2": 11, "small_max": 0, "max_link_buckets_log2": 12},
     {"max_link_buckets_log2": 0, "max_rc_buckets_log2": 0, "small_max": 2048},
     {"cls": [[100, 300, 70]] * 33, "tile_log2": 13},
+    {"row_complete": 1},
+    {"row_complete": 1, "cls": [[2048, 4096, 4096, 64]] * 33, "max_link_buckets_log2": 12},
 ])
 def test_plan_and_workspace_within_their_bounds(tune):
     # The graph form and nsgc_reserve size the plan buffer and the workspace
