@@ -1303,9 +1303,12 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 // buckets of about wave_target packets from its own work queue and
 // aggregates each in a private LDS table.  No wavefront waits for another, so
 // the latency of one wavefront's metadata loads, key gathers and LDS round
-// trips hides behind the work of the others (sixteen per compute unit); the
-// workgroup-wide barriers of k_links are gone.  The emission layout, the
-// overflow sweeps and the statistics are the same as k_links' per-link form.
+// trips hides behind the work of the others (up to twenty per compute unit);
+// the workgroup-wide barriers of k_links are gone.  Lanes holding the same
+// key insert it side by side (the compare-and-swap hands them one slot, and
+// the counts add up in LDS): merging them first with ballots measured slower
+// on 256-packet buckets.  The emission layout, the overflow sweeps and the
+// statistics are the same as k_links' per-link form.
 // ---------------------------------------------------------------------------
 
 constexpr int WAVE_NT = 256;                 // threads per workgroup
@@ -1481,7 +1484,7 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
         mb -= start;                            // base minus exclusive prefix
         for (uint32_t v0 = 0; v0 < elems; v0 += 64 * LINK_MAXU) {
           u64 key[LINK_MAXU];
-          uint32_t h[LINK_MAXU], add[LINK_MAXU];
+          uint32_t h[LINK_MAXU];
           bool ok[LINK_MAXU];
 #pragma unroll
           for (int u = 0; u < LINK_MAXU; ++u) {
@@ -1523,23 +1526,9 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
             const u64 hh = link_pos(key[u]);
             h[u] = uint32_t(hh);
             ok[u] = ok[u] && !(logS && next64(hh, W.logB, logS) != sw);
-            add[u] = 1;
             const bool spc = ok[u] && key[u] == EMPTY64;
             special += __popcll(__ballot(spc));
             if (spc) ok[u] = false;
-            // combine the lanes holding the first valid lane's key
-            const u64 vm = __ballot(ok[u]);
-            if (vm) {
-              const int first = __ffsll(static_cast<unsigned long long>(vm)) - 1;
-              const u64 k0 = (u64(readlane(uint32_t(key[u] >> 32), first)) << 32) |
-                             readlane(uint32_t(key[u]), first);
-              const bool same = ok[u] && key[u] == k0;
-              const uint32_t nsame = __popcll(__ballot(same));
-              if (nsame > 1 && same) {
-                if (int(lane) == first) add[u] = nsame;
-                else ok[u] = false;
-              }
-            }
           }
           int slot[LINK_MAXU];
           bool fresh[LINK_MAXU];
@@ -1547,7 +1536,7 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
             gave_up = true;
 #pragma unroll
           for (int u = 0; u < LINK_MAXU; ++u)
-            if (slot[u] >= 0) lds_add(&tc[slot[u]], add[u]);
+            if (slot[u] >= 0) lds_add(&tc[slot[u]], 1);
 #pragma unroll
           for (int u = 0; u < LINK_MAXU; ++u) {
             const u64 m = __ballot(fresh[u]);
