@@ -25,8 +25,8 @@ hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t
                             uint32_t grid, size_t lds, hipStream_t s);
 hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_buckets, uint32_t grid,
                         size_t lds, hipStream_t s);
-hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t hist, uint32_t rows, uint32_t grid,
-                             size_t lds, hipStream_t s);
+hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t hist, uint32_t rows,
+                             uint32_t order_block, uint32_t grid, size_t lds, hipStream_t s);
 hipError_t launch_heavy(const nsgc_dev_plan* P, uint32_t grid, hipStream_t s);
 size_t lds_heavy_bytes();
 hipError_t launch_order(const nsgc_dev_plan* P, hipStream_t s);
@@ -309,10 +309,14 @@ int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch
     NSGC_HIP(launch_partition(dplan, tile_log2, L.max_link_buckets, grid(hp.itemsA, L.grid_part),
                               L.lds_part, s));
   NSGC_HIP(mark(2));
+  // The phase-C order depends only on the partition's sizes: with wavefront
+  // phase-B items it is computed by an extra workgroup of that kernel, beside
+  // phase B, instead of by k_order after it.
+  const bool order_in_b = part && !hp.entity && linkw;
   if (linkw) {
     const int wc = fixed_grid ? ((variant & 16) ? 1 : 0) : wave_class(hp.wave_rc_max);
     const int r = rows ? 1 : 0;
-    NSGC_HIP(launch_links_wave(dplan, kWaveHist[wc], uint32_t(r),
+    NSGC_HIP(launch_links_wave(dplan, kWaveHist[wc], uint32_t(r), order_in_b ? 1u : 0u,
                                grid((hp.itemsBw + 3) / 4, L.grid_linkw[wc][r]), L.lds_linkw[wc][r],
                                s));
   }
@@ -323,7 +327,7 @@ int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch
   if (part && hp.entity) {
     NSGC_HIP(launch_rowcol_ent(dplan, grid(hp.itemsC, L.grid_rce), L.lds_rce, s));
   } else if (part) {
-    NSGC_HIP(launch_order(dplan, s));
+    if (!order_in_b) NSGC_HIP(launch_order(dplan, s));
     NSGC_HIP(launch_rowcol(dplan, grid(hp.itemsC, L.grid_rc), L.lds_rc, s));
   }
   if (part) NSGC_HIP(launch_finish(dplan, grid(uint32_t(hp.win.size()), L.grid_finish), s));

@@ -472,8 +472,9 @@ __device__ __forceinline__ uint32_t row_bucket(u64 k, uint32_t logB, bool heavy)
 // aligned).  An LDS histogram gives every packet its rank in its bucket, a
 // block scan gives the bucket starts, the keys are placed in LDS in bucket
 // order and leave in full coalesced lines.  The tile's bucket starts go to
-// the bucket-major tile table.  Before its tiles, the grid also clears the
-// phase-C item sizes that phase B sums when the plan orders phase C.
+// the bucket-major tile table.  When the plan orders phase C, a window's
+// first tile also writes the window's phase-C item sizes (packets per row and
+// column bucket in that tile), the only input of the ordering.
 // ---------------------------------------------------------------------------
 
 size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2, uint32_t max_rc_buckets) {
@@ -1396,9 +1397,18 @@ struct WaveQueue {
   }
 };
 
+template <uint32_t NT>
+__device__ __forceinline__ void order_items_by_size(const nsgc_dev_plan* P, uint32_t* cursor);
+
+// `order_block`: workgroup 0 orders the phase-C items (see k_order) and the
+// others aggregate the link buckets.
 __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32_t hist,
-                                                        uint32_t rows) {
+                                                        uint32_t rows, uint32_t order_block) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (order_block && blockIdx.x == 0) {
+    order_items_by_size<WAVE_NT>(P, reinterpret_cast<uint32_t*>(smem));
+    return;
+  }
   const uint32_t w = uniform(threadIdx.x >> 6), lane = lane_id();
   unsigned char* p = smem + size_t(w) * wave_lds_stride(hist, rows);
   u64* tk = reinterpret_cast<u64*>(p);             p += size_t(WAVE_SLOTS) * 8;
@@ -1423,7 +1433,8 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
 
   const uint32_t T = 1u << P->tile_log2;
   const uint32_t items = P->itemsBw;
-  const uint32_t gwaves = gridDim.x * WAVE_WPB, gwave = blockIdx.x * WAVE_WPB + w;
+  const uint32_t gwaves = (gridDim.x - order_block) * WAVE_WPB;
+  const uint32_t gwave = (blockIdx.x - order_block) * WAVE_WPB + w;
   WaveQueue q(gptr(&P->queue[3][0]), gwave, gwaves, P->mapBw ? gptr(P->mapBw) : nullptr);
   for (uint32_t it = q.first(gwave, items); it != NO_ITEM; it = q.next(items)) {
     const uint32_t wi = sload(P->itemwinB + it);
@@ -1758,38 +1769,37 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
 // end.  This matters when the grid gets a few items per workgroup, so the
 // plan asks for it only for batches of at most NSGC_ORDER_MAX items (else
 // the kernel returns and phase C takes the items in their own order).  One
-// workgroup; each thread holds up to NSGC_ORDER_MAX / NSGC_BLOCK
-// consecutive sizes in registers.  The result is a permutation of the items,
-// which is all that the correctness of phase C depends on.
+// workgroup counts and then places the items, each thread a contiguous run
+// of them.  The sizes come from the partition alone, so when the batch has
+// wavefront phase-B items the first workgroup of k_links_wave does this
+// beside phase B; otherwise k_order runs after phase B.  The result is a
+// permutation of the items, which is all that the correctness of phase C
+// depends on.
 // ---------------------------------------------------------------------------
 
-constexpr uint32_t ORDER_PER = NSGC_ORDER_MAX / NSGC_BLOCK;
 // 0 for empty items, else 1 + 2 floor(log2(size)) + the bit below the leading one
 constexpr uint32_t ORDER_CLASSES = 65;
 
-__global__ __launch_bounds__(NSGC_BLOCK) void k_order(nsgc_dev_plan* P) {
-  __shared__ uint32_t cursor[ORDER_CLASSES];
+__device__ __forceinline__ uint32_t order_class(uint32_t v) {
+  if (!v) return 0u;
+  const uint32_t lg = 31u - uint32_t(__builtin_clz(v));
+  return 1u + 2u * lg + (lg ? (v >> (lg - 1u)) & 1u : 0u);
+}
+
+// The ordering by one workgroup of NT threads, `cursor` in LDS
+// (ORDER_CLASSES words): a count pass and a placement pass over the sizes,
+// each thread taking a contiguous run of items (read twice, from L2).
+template <uint32_t NT>
+__device__ __forceinline__ void order_items_by_size(const nsgc_dev_plan* P, uint32_t* cursor) {
   const uint32_t n = P->itemsC;
   if (!P->order_items || n == 0) return;
   const NSGC_GLOBAL uint32_t* sz = gptr(P->rcsize);
   NSGC_GLOBAL uint32_t* order = gptr(P->order);
-  if (threadIdx.x < ORDER_CLASSES) cursor[threadIdx.x] = 0;
+  for (uint32_t c = threadIdx.x; c < ORDER_CLASSES; c += NT) cursor[c] = 0;
   __syncthreads();
-  const uint32_t per = (n + NSGC_BLOCK - 1) / NSGC_BLOCK;   // <= ORDER_PER
-  const uint32_t beg = threadIdx.x * per;
-  uint32_t cls[ORDER_PER];
-#pragma unroll
-  for (uint32_t k = 0; k < ORDER_PER; ++k) {
-    const uint32_t i = beg + k;
-    const uint32_t v = (k < per && i < n) ? sz[i] : 0u;
-    if (v) {
-      const uint32_t lg = 31u - uint32_t(__builtin_clz(v));
-      cls[k] = 1u + 2u * lg + (lg ? (v >> (lg - 1u)) & 1u : 0u);
-    } else {
-      cls[k] = 0u;
-    }
-    if (k < per && i < n) lds_add(&cursor[cls[k]], 1);
-  }
+  const uint32_t per = (n + NT - 1) / NT;
+  const uint32_t beg = min(n, threadIdx.x * per), end = min(n, beg + per);
+  for (uint32_t i = beg; i < end; ++i) lds_add(&cursor[order_class(sz[i])], 1);
   __syncthreads();
   if (threadIdx.x == 0) {   // class starts, largest class first
     uint32_t run = 0;
@@ -1800,11 +1810,12 @@ __global__ __launch_bounds__(NSGC_BLOCK) void k_order(nsgc_dev_plan* P) {
     }
   }
   __syncthreads();
-#pragma unroll
-  for (uint32_t k = 0; k < ORDER_PER; ++k) {
-    const uint32_t i = beg + k;
-    if (k < per && i < n) order[lds_add(&cursor[cls[k]], 1)] = i;
-  }
+  for (uint32_t i = beg; i < end; ++i) order[lds_add(&cursor[order_class(sz[i])], 1)] = i;
+}
+
+__global__ __launch_bounds__(NSGC_BLOCK) void k_order(nsgc_dev_plan* P) {
+  __shared__ uint32_t cursor[ORDER_CLASSES];
+  order_items_by_size<NSGC_BLOCK>(P, cursor);
 }
 
 // ---------------------------------------------------------------------------
@@ -2367,10 +2378,10 @@ hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_bu
   return hipGetLastError();
 }
 
-hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t hist, uint32_t rows, uint32_t grid,
-                             size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_links_wave, dim3(grid), dim3(WAVE_NT), lds, s, const_cast<nsgc_dev_plan*>(P),
-                     hist, rows);
+hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t hist, uint32_t rows,
+                             uint32_t order_block, uint32_t grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(k_links_wave, dim3(grid + order_block), dim3(WAVE_NT), lds, s,
+                     const_cast<nsgc_dev_plan*>(P), hist, rows, order_block);
   return hipGetLastError();
 }
 
