@@ -22,7 +22,7 @@
 namespace nsgc {
 hipError_t launch_small(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipStream_t s);
 hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t max_link_buckets,
-                            uint32_t grid, size_t lds, hipStream_t s);
+                            bool rows, uint32_t grid, size_t lds, hipStream_t s);
 hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_buckets, uint32_t grid,
                         size_t lds, hipStream_t s);
 hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t hist, uint32_t rows,
@@ -251,7 +251,7 @@ int launch_params(DevCtx* c, const nsgc_tune& t, Launch* out) {
   // the workgroup kernels' 512-thread workgroups
   for (int k = 0; k < 2; ++k)
     for (int r = 0; r < 2; ++r)
-      if ((rc = resident_cap(c, 5, tile, L.lds_linkw[k][r], 4 * want, &L.grid_linkw[k][r])) !=
+      if ((rc = resident_cap(c, r ? 7 : 5, tile, L.lds_linkw[k][r], 4 * want, &L.grid_linkw[k][r])) !=
           NSGC_OK)
         return rc;
   L.grid_finish = uint32_t(c->cus) * 4;
@@ -306,7 +306,7 @@ int enqueue_kernels(const HostPlan& hp, const nsgc_dev_plan* dplan, const Launch
   NSGC_HIP(mark(1));
   if (rows) NSGC_HIP(launch_heavy(dplan, grid(uint32_t(hp.win.size()), L.grid_heavy), s));
   if (part)
-    NSGC_HIP(launch_partition(dplan, tile_log2, L.max_link_buckets, grid(hp.itemsA, L.grid_part),
+    NSGC_HIP(launch_partition(dplan, tile_log2, L.max_link_buckets, rows, grid(hp.itemsA, L.grid_part),
                               L.lds_part, s));
   NSGC_HIP(mark(2));
   // The phase-C order depends only on the partition's sizes: with wavefront

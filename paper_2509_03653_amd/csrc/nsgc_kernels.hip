@@ -483,7 +483,9 @@ size_t lds_part_bytes(uint32_t max_link_buckets, uint32_t tile_log2, uint32_t ma
          NSGC_HEAVY_SLOTS * 4;
 }
 
-template <int PER, int NT = NSGC_BLOCK>
+// ROWS: the launch's batch has row-complete windows (the other instances
+// carry none of their code).
+template <int PER, int NT = NSGC_BLOCK, bool ROWS = false>
 __global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restrict__ P,
                                                   uint32_t max_link_buckets) {
   static_assert(PER % 4 == 0, "PER must be a multiple of 4");
@@ -516,7 +518,7 @@ __global__ __launch_bounds__(NT) void k_partition(const nsgc_dev_plan* __restric
     for (uint32_t i = threadIdx.x; i < B; i += NT) hist[i] = 0;
     if (sample)
       for (uint32_t i = threadIdx.x; i < R + C; i += NT) rch[i] = 0;
-    const bool rows = W.rows != 0;
+    const bool rows = ROWS && W.rows != 0;
     if (rows)
       for (uint32_t i = threadIdx.x; i < NSGC_HEAVY_SLOTS; i += NT)
         hv[i] = gptr(P->heavy)[u64(W.counter) * NSGC_HEAVY_SLOTS + i];
@@ -1401,9 +1403,12 @@ template <uint32_t NT>
 __device__ __forceinline__ void order_items_by_size(const nsgc_dev_plan* P, uint32_t* cursor);
 
 // `order_block`: workgroup 0 orders the phase-C items (see k_order) and the
-// others aggregate the link buckets.
+// others aggregate the link buckets.  ROWS: the batch has row-complete
+// windows (row tables in LDS; the other instance carries none of their code).
+template <bool ROWS>
 __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32_t hist,
-                                                        uint32_t rows, uint32_t order_block) {
+                                                        uint32_t order_block) {
+  constexpr uint32_t rows = ROWS ? 1u : 0u;
   extern __shared__ __align__(16) unsigned char smem[];
   if (order_block && blockIdx.x == 0) {
     order_items_by_size<WAVE_NT>(P, reinterpret_cast<uint32_t*>(smem));
@@ -2355,16 +2360,23 @@ hipError_t launch_small(const nsgc_dev_plan* P, uint32_t grid, size_t lds, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t max_link_buckets,
-                            uint32_t grid, size_t lds, hipStream_t s) {
+template <bool ROWS>
+hipError_t launch_partition_t(const nsgc_dev_plan* P, uint32_t tile_log2,
+                              uint32_t max_link_buckets, uint32_t grid, size_t lds, hipStream_t s) {
   switch (tile_log2) {
-    case 11: hipLaunchKernelGGL(k_partition<4>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
-    case 12: hipLaunchKernelGGL(k_partition<8>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
-    case 13: hipLaunchKernelGGL(k_partition<16>, dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
-    case 14: hipLaunchKernelGGL((k_partition<32 / PART14_SCALE, NSGC_BLOCK * PART14_SCALE>), dim3(grid), dim3(NSGC_BLOCK * PART14_SCALE), lds, s, P, max_link_buckets); break;
+    case 11: hipLaunchKernelGGL((k_partition<4, NSGC_BLOCK, ROWS>), dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
+    case 12: hipLaunchKernelGGL((k_partition<8, NSGC_BLOCK, ROWS>), dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
+    case 13: hipLaunchKernelGGL((k_partition<16, NSGC_BLOCK, ROWS>), dim3(grid), dim3(NSGC_BLOCK), lds, s, P, max_link_buckets); break;
+    case 14: hipLaunchKernelGGL((k_partition<32 / PART14_SCALE, NSGC_BLOCK * PART14_SCALE, ROWS>), dim3(grid), dim3(NSGC_BLOCK * PART14_SCALE), lds, s, P, max_link_buckets); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_partition(const nsgc_dev_plan* P, uint32_t tile_log2, uint32_t max_link_buckets,
+                            bool rows, uint32_t grid, size_t lds, hipStream_t s) {
+  return rows ? launch_partition_t<true>(P, tile_log2, max_link_buckets, grid, lds, s)
+              : launch_partition_t<false>(P, tile_log2, max_link_buckets, grid, lds, s);
 }
 
 hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_buckets, uint32_t grid,
@@ -2380,8 +2392,12 @@ hipError_t launch_links(const nsgc_dev_plan* P, bool combine, uint32_t max_rc_bu
 
 hipError_t launch_links_wave(const nsgc_dev_plan* P, uint32_t hist, uint32_t rows,
                              uint32_t order_block, uint32_t grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_links_wave, dim3(grid + order_block), dim3(WAVE_NT), lds, s,
-                     const_cast<nsgc_dev_plan*>(P), hist, rows, order_block);
+  if (rows)
+    hipLaunchKernelGGL(k_links_wave<true>, dim3(grid + order_block), dim3(WAVE_NT), lds, s,
+                       const_cast<nsgc_dev_plan*>(P), hist, order_block);
+  else
+    hipLaunchKernelGGL(k_links_wave<false>, dim3(grid + order_block), dim3(WAVE_NT), lds, s,
+                       const_cast<nsgc_dev_plan*>(P), hist, order_block);
   return hipGetLastError();
 }
 
@@ -2426,12 +2442,13 @@ hipError_t resident_blocks(int which, uint32_t tile_log2, size_t lds, int* block
     case 2: f = reinterpret_cast<const void*>(&k_links<false>); break;
     case 4: f = reinterpret_cast<const void*>(&k_links<true>); break;
     case 3: f = reinterpret_cast<const void*>(&k_rowcol); break;
-    case 5: f = reinterpret_cast<const void*>(&k_links_wave); break;
+    case 5: f = reinterpret_cast<const void*>(&k_links_wave<false>); break;
+    case 7: f = reinterpret_cast<const void*>(&k_links_wave<true>); break;
     case 6: f = reinterpret_cast<const void*>(&k_rowcol_ent); break;
     default: return hipErrorInvalidValue;
   }
   const int threads = which == 1 && tile_log2 == 14 ? NSGC_BLOCK * PART14_SCALE
-                      : which == 5                  ? WAVE_NT
+                      : which == 5 || which == 7    ? WAVE_NT
                                                     : NSGC_BLOCK;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, threads, lds);
 }
@@ -2440,11 +2457,16 @@ hipError_t allow_large_lds(size_t bytes) {
   const int b = int(bytes);
   const void* fns[] = {
       reinterpret_cast<const void*>(&k_small),         reinterpret_cast<const void*>(&k_links<false>),
-      reinterpret_cast<const void*>(&k_links<true>),   reinterpret_cast<const void*>(&k_links_wave),
+      reinterpret_cast<const void*>(&k_links<true>),   reinterpret_cast<const void*>(&k_links_wave<false>),
+      reinterpret_cast<const void*>(&k_links_wave<true>),
       reinterpret_cast<const void*>(&k_rowcol_ent),    reinterpret_cast<const void*>(&k_heavy),
       reinterpret_cast<const void*>(&k_rowcol),        reinterpret_cast<const void*>(&k_partition<4>),
       reinterpret_cast<const void*>(&k_partition<8>),  reinterpret_cast<const void*>(&k_partition<16>),
-      reinterpret_cast<const void*>(&k_partition<32 / PART14_SCALE, NSGC_BLOCK * PART14_SCALE>)};
+      reinterpret_cast<const void*>(&k_partition<32 / PART14_SCALE, NSGC_BLOCK * PART14_SCALE>),
+      reinterpret_cast<const void*>(&k_partition<4, NSGC_BLOCK, true>),
+      reinterpret_cast<const void*>(&k_partition<8, NSGC_BLOCK, true>),
+      reinterpret_cast<const void*>(&k_partition<16, NSGC_BLOCK, true>),
+      reinterpret_cast<const void*>(&k_partition<32 / PART14_SCALE, NSGC_BLOCK * PART14_SCALE, true>)};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
