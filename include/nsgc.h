@@ -49,7 +49,11 @@
  *     nsgc_last_hip_error() gives the hipError_t.
  *   - The library keeps per-(device, stream) workspaces, so calls on
  *     different streams may overlap; calls on one stream run in order.  All
- *     entry points are thread-safe.
+ *     entry points are thread-safe: host threads calling on different
+ *     streams plan and enqueue concurrently (a lock per stream, per graph
+ *     object and per device's fixed scratch; the shared state is only looked
+ *     up under a process-wide lock), calls on one stream take turns.
+ *     nsgc_graph_destroy must not overlap a launch of the same graph.
  *   - The direct forms (nsgc_window_stats, _plain, _timed) must not be
  *     called on a stream that is being captured: they return
  *     NSGC_ERR_CAPTURING with nothing enqueued.  Their plan upload reads a

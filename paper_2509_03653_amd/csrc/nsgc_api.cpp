@@ -62,8 +62,11 @@ int hip_fail(hipError_t e) {
 
 constexpr int kStages = 4;
 
-// Device buffers and staging of one (device, stream) pair or graph instance.
+// Device buffers and staging of one (device, stream) pair.  A call works on
+// its slot under the slot's own lock; slots are never deleted (nsgc_release
+// frees their buffers), so a slot pointer stays valid once looked up.
 struct Slot {
+  std::mutex mu;
   char* plan_dev = nullptr;
   size_t plan_cap = 0;
   char* ws = nullptr;
@@ -82,6 +85,7 @@ struct Slot {
 // the event after its last launch (a call on another stream waits for it on
 // the device, since every call shares the device's one scratch array).
 struct FixedState {
+  std::mutex mu;
   std::vector<char> stage;
   hipEvent_t copied = nullptr;
   hipEvent_t done = nullptr;
@@ -99,6 +103,12 @@ struct DevCtx {
   FixedState fixed;
 };
 
+// Guards the process-wide state below (device contexts, their slot maps and
+// occupancy cache, the tuning and the plain-mode switch).  Calls hold it only
+// to look these up; planning, uploads and launches run under the lock of the
+// call's slot (or graph, or the device's fixed scratch), so calls on
+// different streams plan and enqueue concurrently.  Lock order: g_mu before a
+// slot's lock, and no code holding a slot's lock takes g_mu.
 std::mutex g_mu;
 std::map<int, DevCtx*> g_devs;
 nsgc_tune g_tune;
@@ -368,11 +378,9 @@ int get_slot(DevCtx* c, hipStream_t s, Slot** out) {
 }
 
 // Upload one plan into slot `sl` and launch it.
-int run_plan(DevCtx* c, Slot* sl, const HostPlan& hp, const nsgc_tune& t, const uint32_t* src,
+int run_plan(DevCtx* c, Slot* sl, const HostPlan& hp, const Launch& L, const uint32_t* src,
              const uint32_t* dst, void* out, hipStream_t s, const hipEvent_t* ev = nullptr) {
-  Launch L;
-  int rc = launch_params(c, t, &L);
-  if (rc != NSGC_OK) return rc;
+  int rc;
   const size_t pbytes = hp.plan_bytes();
   const WsLayout lay = hp.layout();
   if ((rc = ensure_device(&sl->plan_dev, &sl->plan_cap, pbytes, s)) != NSGC_OK) return rc;
@@ -422,32 +430,52 @@ size_t workspace_bound(int64_t max_packets, int64_t max_windows, const nsgc_tune
   return b;
 }
 
-// The batched form (caller holds g_mu, arguments validated, num_windows > 0).
-int batched_locked(const uint32_t* src, const uint32_t* dst, const int64_t* window_offsets,
-                   int64_t num_windows, nsgc_stats* out_stats, hipStream_t s) {
-  const nsgc_tune t = current_tune();
+// What a call on (current device, s) reads from the shared state, looked up
+// under g_mu: the tuning in force (entity calls adjust it), the device
+// context, the stream's slot, the launch shapes and the plain-mode switch.
+struct CallCtx {
+  nsgc_tune t;
+  DevCtx* c = nullptr;
+  Slot* sl = nullptr;
+  Launch L;
+  bool plain = false;
+};
+
+int begin_call(hipStream_t s, CallCtx* cc, bool entity = false, bool launch = true) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  cc->t = current_tune();
+  if (entity) {
+    cc->t.combine_probes = 0;                              // links are listed by the per-link emission
+    cc->t.rc_slots_log2 = std::min(cc->t.rc_slots_log2, 12);   // two phase-C tables per workgroup
+  }
+  cc->plain = g_plain_mode;
+  int rc;
+  if ((rc = get_ctx(&cc->c)) != NSGC_OK) return rc;
+  if ((rc = get_slot(cc->c, s, &cc->sl)) != NSGC_OK) return rc;
+  return launch ? launch_params(cc->c, cc->t, &cc->L) : NSGC_OK;
+}
+
+// The batched form (caller holds the slot's lock, arguments validated,
+// num_windows > 0).
+int batched_locked(const CallCtx& cc, const uint32_t* src, const uint32_t* dst,
+                   const int64_t* window_offsets, int64_t num_windows, nsgc_stats* out_stats,
+                   hipStream_t s) {
   HostPlan hp;
   int rc;
-  if ((rc = make_plan(window_offsets, num_windows, t, &hp)) != NSGC_OK) return rc;
-  DevCtx* c = nullptr;
-  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
-  Slot* sl = nullptr;
-  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
-  return run_plan(c, sl, hp, t, src, dst, out_stats, s);
+  if ((rc = make_plan(window_offsets, num_windows, cc.t, &hp)) != NSGC_OK) return rc;
+  return run_plan(cc.c, cc.sl, hp, cc.L, src, dst, out_stats, s);
 }
 
 // The plain form: one plan and one launch sequence per window (caller holds
-// g_mu, arguments validated, num_windows > 0).
-int plain_locked(const uint32_t* src, const uint32_t* dst, const int64_t* window_offsets,
-                 int64_t num_windows, nsgc_stats* out_stats, hipStream_t s) {
-  const nsgc_tune t = current_tune();
-  DevCtx* c = nullptr;
+// the slot's lock, arguments validated, num_windows > 0).
+int plain_locked(const CallCtx& cc, const uint32_t* src, const uint32_t* dst,
+                 const int64_t* window_offsets, int64_t num_windows, nsgc_stats* out_stats,
+                 hipStream_t s) {
+  const nsgc_tune& t = cc.t;
+  DevCtx* c = cc.c;
+  Slot* sl = cc.sl;
+  const Launch& L = cc.L;
   int rc;
-  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
-  Slot* sl = nullptr;
-  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
-  Launch L;
-  if ((rc = launch_params(c, t, &L)) != NSGC_OK) return rc;
 
   // One plan per window, all uploaded with one copy; the windows then run one
   // launch sequence each, in order, sharing one workspace.
@@ -483,17 +511,16 @@ int plain_locked(const uint32_t* src, const uint32_t* dst, const int64_t* window
 }
 
 // Pre-size the workspace, plan buffer and staging ring of (current device, s).
-int reserve_locked(int64_t max_packets, int64_t max_windows, hipStream_t s) {
+int reserve_call(int64_t max_packets, int64_t max_windows, hipStream_t s) {
   if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
-  const nsgc_tune t = current_tune();
-  DevCtx* c = nullptr;
+  CallCtx cc;
   int rc;
-  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
-  Slot* sl = nullptr;
-  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
-  const size_t pb = plan_bound(max_packets, max_windows, t);
+  if ((rc = begin_call(s, &cc, false, false)) != NSGC_OK) return rc;
+  Slot* sl = cc.sl;
+  std::lock_guard<std::mutex> lock(sl->mu);
+  const size_t pb = plan_bound(max_packets, max_windows, cc.t);
   if ((rc = ensure_device(&sl->plan_dev, &sl->plan_cap, pb, s)) != NSGC_OK) return rc;
-  if ((rc = ensure_device(&sl->ws, &sl->ws_cap, workspace_bound(max_packets, max_windows, t), s)) !=
+  if ((rc = ensure_device(&sl->ws, &sl->ws_cap, workspace_bound(max_packets, max_windows, cc.t), s)) !=
       NSGC_OK)
     return rc;
   for (int k = 0; k < kStages; ++k) {
@@ -528,18 +555,22 @@ int run_fixed_scratch(const uint32_t* src, const uint32_t* dst, const int64_t* w
   if (rc != NSGC_OK || num_windows == 0) return rc;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
-  std::lock_guard<std::mutex> lock(g_mu);
-  const nsgc_tune t = current_tune();
+  nsgc_tune t;
+  DevCtx* c = nullptr;
+  Launch L;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    t = current_tune();
+    if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
+    if ((rc = launch_params(c, t, &L)) != NSGC_OK) return rc;
+  }
   HostPlan hp;
   if ((rc = make_plan(window_offsets, num_windows, t, &hp)) != NSGC_OK) return rc;
   const size_t pbytes = hp.plan_bytes();
   const WsLayout lay = hp.layout();
   if (pbytes > plan_cap || lay.total > ws_cap) return NSGC_ERR_TOO_LARGE;
-  DevCtx* c = nullptr;
-  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
-  Launch L;
-  if ((rc = launch_params(c, t, &L)) != NSGC_OK) return rc;
   FixedState& f = c->fixed;
+  std::lock_guard<std::mutex> lock(f.mu);
   if (!f.copied) NSGC_HIP(hipEventCreateWithFlags(&f.copied, hipEventDisableTiming));
   if (!f.done) NSGC_HIP(hipEventCreateWithFlags(&f.done, hipEventDisableTiming));
   if (f.stage.size() < plan_cap) f.stage.resize(plan_cap);
@@ -593,9 +624,11 @@ int nsgc_window_stats(const uint32_t* src, const uint32_t* dst, const int64_t* w
   // workspace that later calls reuse, so a captured call could not be
   // replayed safely: capture the graph form (nsgc_graph_*) instead.
   if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
-  std::lock_guard<std::mutex> lock(g_mu);
-  if (g_plain_mode) return plain_locked(src, dst, window_offsets, num_windows, out_stats, s);
-  return batched_locked(src, dst, window_offsets, num_windows, out_stats, s);
+  CallCtx cc;
+  if ((rc = begin_call(s, &cc)) != NSGC_OK) return rc;
+  std::lock_guard<std::mutex> lock(cc.sl->mu);
+  if (cc.plain) return plain_locked(cc, src, dst, window_offsets, num_windows, out_stats, s);
+  return batched_locked(cc, src, dst, window_offsets, num_windows, out_stats, s);
 }
 
 int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
@@ -605,8 +638,10 @@ int nsgc_window_stats_plain(const uint32_t* src, const uint32_t* dst,
   if (rc != NSGC_OK || num_windows == 0) return rc;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
-  std::lock_guard<std::mutex> lock(g_mu);
-  return plain_locked(src, dst, window_offsets, num_windows, out_stats, s);
+  CallCtx cc;
+  if ((rc = begin_call(s, &cc)) != NSGC_OK) return rc;
+  std::lock_guard<std::mutex> lock(cc.sl->mu);
+  return plain_locked(cc, src, dst, window_offsets, num_windows, out_stats, s);
 }
 
 namespace {
@@ -631,12 +666,11 @@ int entities_call(const uint32_t* src, const uint32_t* dst, const int64_t* windo
       if ((rc = check_list_offsets(list_off[k], num_windows, lists[k])) != NSGC_OK) return rc;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
-  std::lock_guard<std::mutex> lock(g_mu);
-  nsgc_tune t = current_tune();
-  t.combine_probes = 0;                                // links are listed by the per-link emission
-  t.rc_slots_log2 = std::min(t.rc_slots_log2, 12);     // two phase-C tables per workgroup
+  CallCtx cc;
+  if ((rc = begin_call(s, &cc, true)) != NSGC_OK) return rc;
+  std::lock_guard<std::mutex> lock(cc.sl->mu);
   HostPlan hp;
-  if ((rc = make_plan(window_offsets, num_windows, t, &hp, true)) != NSGC_OK) return rc;
+  if ((rc = make_plan(window_offsets, num_windows, cc.t, &hp, true)) != NSGC_OK) return rc;
   hp.ent_cur.assign(size_t(num_windows) * 3, 0);
   hp.ent_end.assign(size_t(num_windows) * 3, 0);
   if (list_off) {
@@ -650,14 +684,8 @@ int entities_call(const uint32_t* src, const uint32_t* dst, const int64_t* windo
     hp.ent_dst = lists[2];
   }
   hp.ent_counts = counts;
-  DevCtx* c = nullptr;
-  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
-  Slot* sl = nullptr;
-  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
-  Launch L;
-  if ((rc = launch_params(c, t, &L)) != NSGC_OK) return rc;
-  if (!hp.win.empty() && L.grid_rce == 0) return NSGC_ERR_INVALID_ARG;
-  return run_plan(c, sl, hp, t, src, dst, nullptr, s);
+  if (!hp.win.empty() && cc.L.grid_rce == 0) return NSGC_ERR_INVALID_ARG;
+  return run_plan(cc.c, cc.sl, hp, cc.L, src, dst, nullptr, s);
 }
 
 }  // namespace
@@ -687,12 +715,12 @@ int nsgc_anonymize(const uint32_t* src, const uint32_t* dst, int64_t num_packets
   if (num_packets > 0 && (!src || !dst || !anon_src || !anon_dst)) return NSGC_ERR_INVALID_ARG;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
-  std::lock_guard<std::mutex> lock(g_mu);
-  DevCtx* c = nullptr;
+  CallCtx cc;
   int rc;
-  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
-  Slot* sl = nullptr;
-  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
+  if ((rc = begin_call(s, &cc, false, false)) != NSGC_OK) return rc;
+  DevCtx* c = cc.c;
+  Slot* sl = cc.sl;
+  std::lock_guard<std::mutex> lock(sl->mu);
   const unsigned long long n = (unsigned long long)num_packets;
   if ((rc = ensure_device(&sl->ws, &sl->ws_cap, anonymize_bytes(n), s)) != NSGC_OK) return rc;
   NSGC_HIP(anonymize(src, dst, n, seed, anon_src, anon_dst,
@@ -720,19 +748,17 @@ int nsgc_window_stats_timed(const uint32_t* src, const uint32_t* dst,
   if (rc != NSGC_OK) return rc;
   for (int i = 0; i < 5; ++i) phase_ms[i] = 0.0f;
   if (num_windows == 0) return NSGC_OK;
-  std::lock_guard<std::mutex> lock(g_mu);
-  const nsgc_tune t = current_tune();
-  HostPlan hp;
-  if ((rc = make_plan(window_offsets, num_windows, t, &hp)) != NSGC_OK) return rc;
-  DevCtx* c = nullptr;
-  if ((rc = get_ctx(&c)) != NSGC_OK) return rc;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   if (stream_capturing(s)) return NSGC_ERR_CAPTURING;
-  Slot* sl = nullptr;
-  if ((rc = get_slot(c, s, &sl)) != NSGC_OK) return rc;
+  CallCtx cc;
+  if ((rc = begin_call(s, &cc)) != NSGC_OK) return rc;
+  Slot* sl = cc.sl;
+  std::lock_guard<std::mutex> lock(sl->mu);
+  HostPlan hp;
+  if ((rc = make_plan(window_offsets, num_windows, cc.t, &hp)) != NSGC_OK) return rc;
   for (int i = 0; i < 6; ++i)
     if (!sl->phase_ev[i]) NSGC_HIP(hipEventCreate(&sl->phase_ev[i]));
-  if ((rc = run_plan(c, sl, hp, t, src, dst, out_stats, s, sl->phase_ev)) != NSGC_OK) return rc;
+  if ((rc = run_plan(cc.c, sl, hp, cc.L, src, dst, out_stats, s, sl->phase_ev)) != NSGC_OK) return rc;
   NSGC_HIP(hipEventSynchronize(sl->phase_ev[5]));
   for (int i = 0; i < 5; ++i)
     NSGC_HIP(hipEventElapsedTime(&phase_ms[i], sl->phase_ev[i], sl->phase_ev[i + 1]));
@@ -741,14 +767,12 @@ int nsgc_window_stats_timed(const uint32_t* src, const uint32_t* dst,
 
 int nsgc_reserve(int64_t max_packets, int64_t max_windows) {
   if (max_packets < 0 || max_windows < 0) return NSGC_ERR_INVALID_ARG;
-  std::lock_guard<std::mutex> lock(g_mu);
-  return reserve_locked(max_packets, max_windows, nullptr);
+  return reserve_call(max_packets, max_windows, nullptr);
 }
 
 int nsgc_reserve_stream(int64_t max_packets, int64_t max_windows, void* stream) {
   if (max_packets < 0 || max_windows < 0) return NSGC_ERR_INVALID_ARG;
-  std::lock_guard<std::mutex> lock(g_mu);
-  return reserve_locked(max_packets, max_windows, static_cast<hipStream_t>(stream));
+  return reserve_call(max_packets, max_windows, static_cast<hipStream_t>(stream));
 }
 
 int nsgc_release(void) {
@@ -758,19 +782,28 @@ int nsgc_release(void) {
   auto it = g_devs.find(dev);
   if (it == g_devs.end()) return NSGC_OK;
   NSGC_HIP(hipDeviceSynchronize());
+  // the slots stay (a call may hold a pointer to one); their buffers go
   for (auto& kv : it->second->slots) {
     Slot* sl = kv.second;
+    std::lock_guard<std::mutex> slock(sl->mu);
     if (sl->plan_dev) (void)hipFree(sl->plan_dev);
     if (sl->ws) (void)hipFree(sl->ws);
+    sl->plan_dev = sl->ws = nullptr;
+    sl->plan_cap = sl->ws_cap = 0;
     for (int k = 0; k < kStages; ++k) {
       if (sl->stage[k]) (void)hipHostFree(sl->stage[k]);
       if (sl->ev[k]) (void)hipEventDestroy(sl->ev[k]);
+      sl->stage[k] = nullptr;
+      sl->stage_cap[k] = 0;
+      sl->ev[k] = nullptr;
+      sl->ev_used[k] = false;
     }
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 6; ++k) {
       if (sl->phase_ev[k]) (void)hipEventDestroy(sl->phase_ev[k]);
-    delete sl;
+      sl->phase_ev[k] = nullptr;
+    }
+    sl->next = 0;
   }
-  it->second->slots.clear();
   return NSGC_OK;
 }
 
@@ -861,6 +894,7 @@ int nsgc_plan_inspect(const int64_t* window_offsets, int64_t num_windows, int32_
 }  // extern "C"
 
 struct nsgc_graph {
+  std::mutex mu;   // launches of one graph object (plans, instances, workspace)
   int device = 0;
   nsgc_tune tune;
   Launch L;
@@ -1002,7 +1036,7 @@ int nsgc_graph_launch(nsgc_graph* g, const uint32_t* src, const uint32_t* dst,
   if (rc != NSGC_OK || num_windows == 0) return rc;
   if (num_windows > g->max_windows) return NSGC_ERR_INVALID_ARG;
   if (window_offsets[num_windows] - window_offsets[0] > g->max_packets) return NSGC_ERR_INVALID_ARG;
-  std::lock_guard<std::mutex> lock(g_mu);
+  std::lock_guard<std::mutex> lock(g->mu);
   const hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
   NSGC_HIP(hipGetDevice(&dev));
@@ -1041,8 +1075,7 @@ int nsgc_graph_launch(nsgc_graph* g, const uint32_t* src, const uint32_t* dst,
 
 int nsgc_graph_destroy(nsgc_graph* g) {
   if (!g) return NSGC_ERR_INVALID_ARG;
-  std::lock_guard<std::mutex> lock(g_mu);
-  destroy_graph(g);
+  destroy_graph(g);   // no launch of g may overlap (see nsgc.h)
   return NSGC_OK;
 }
 

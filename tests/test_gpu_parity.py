@@ -315,6 +315,61 @@ def test_stream_argument_and_out_reuse():
     assert_same(out.cpu().numpy().view(np.uint64), want, "side stream")
 
 
+def test_concurrent_host_threads_on_their_own_streams():
+    # host threads plan and enqueue at the same time, each on its own stream
+    # (a lock per stream), while another thread switches the tuning (which
+    # never changes a result); every call must return the oracle's statistics
+    import threading
+
+    import torch
+    cases = []
+    for seed, windows, log2 in ((21, 5, 15), (22, 9, 13), (23, 2, 17)):
+        wl = synth.zipf_batch(seed=seed, num_windows=windows, log2_window=log2)
+        src, dst = wl.generate()
+        cases.append((torch.from_numpy(src.view(np.int32)).cuda(),
+                      torch.from_numpy(dst.view(np.int32)).cuda(), wl.offsets,
+                      oracle.window_stats(src, dst, wl.offsets, threads=8)))
+    torch.cuda.synchronize()
+    errors = []
+    stop = threading.Event()
+
+    def worker(k):
+        s, d, off, want = cases[k]
+        st = torch.cuda.Stream()
+        try:
+            for it in range(25):
+                out = torch.full((len(off) - 1, 9), -1, dtype=torch.int64, device="cuda")
+                fn = (nsgc.window_stats, nsgc.window_stats_plain)[it % 5 == 4]
+                fn(s, d, off, out=out, stream=st)
+                st.synchronize()
+                got = out.cpu().numpy().view(np.uint64)
+                if not np.array_equal(got, want):
+                    errors.append((k, it))
+        except Exception as e:   # reported below, on the main thread
+            errors.append((k, repr(e)))
+
+    def tuner():
+        a = nsgc.default_tune()
+        b = nsgc.Tune.from_dict(dict(a.to_dict(), blocks_per_cu=2, small_max=512))
+        i = 0
+        while not stop.is_set():
+            nsgc.set_tune((a, b)[i % 2])
+            i += 1
+
+    say("[gpu] three threads on three streams, one switching the tuning")
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(len(cases))]
+    tt = threading.Thread(target=tuner)
+    tt.start()
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(120)
+    stop.set()
+    tt.join(10)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors
+
+
 def test_heavy_links_split_entries():
     # links with more packets than an emission entry's packet field holds
     # (2^19 - 1) are emitted as several entries; every path must sum them
