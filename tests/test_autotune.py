@@ -35,6 +35,12 @@ def test_apply_point_scales_only_present_classes():
     assert d["blocks_per_cu"] == 3
     assert d["cls"][17][0] == 2 * base["cls"][17][0]
     assert d["cls"][17][1] == base["cls"][17][1] // 2
+    assert d["cls"][17][2] == base["cls"][17][2] // 2
+    # row_scale multiplies the row target on top of rc_scale, in any key order
+    for pt in ({"row_scale": 2.0, "rc_scale": 0.5}, {"rc_scale": 0.5, "row_scale": 2.0}):
+        e = at.apply_point(base, pt, [17])
+        assert e["cls"][17][1] == base["cls"][17][1]
+        assert e["cls"][17][2] == base["cls"][17][2] // 2
     assert d["cls"][17][3] == 0 and base["cls"][17][3] > 0
     assert d["cls"][16] == base["cls"][16]
     nsgc.Tune.from_dict(d)   # a valid tuning structure
@@ -56,7 +62,7 @@ def test_search_finds_the_separable_optimum():
     # cost model with a known optimum; coordinate descent must reach it
     opt = {"blocks_per_cu": 3, "link_slots_log2": 11, "rc_slots_log2": 13, "tile_log2": 14,
            "small_max": 512, "link_scale": 2.0, "max_link_buckets_log2": 11, "rc_scale": 0.5,
-           "wave_target": 128, "combine_probes": 64}
+           "row_scale": 2.0, "wave_target": 128, "combine_probes": 64}
     assert set(opt) == {k for k, _ in at.SPACE}
     calls = []
 
