@@ -1306,7 +1306,7 @@ __global__ __launch_bounds__(NSGC_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 // buckets of about wave_target packets from its own work queue and
 // aggregates each in a private LDS table.  No wavefront waits for another, so
 // the latency of one wavefront's metadata loads, key gathers and LDS round
-// trips hides behind the work of the others (up to twenty per compute unit);
+// trips hides behind the work of the others (up to 24 per compute unit);
 // the workgroup-wide barriers of k_links are gone.  Lanes holding the same
 // key insert it side by side (the compare-and-swap hands them one slot, and
 // the counts add up in LDS): merging them first with ballots measured slower
@@ -1326,9 +1326,13 @@ constexpr uint32_t WAVE_ROWS = NSGC_WAVE_ROW_SLOTS;
 // (`hist` per view: one more than the launch's largest row or column bucket
 // count, so that batches of small windows fit more wavefronts per CU), the
 // occupied-slot list and, in launches with row-complete windows, the row
-// table (hashed source id, links << 20 | packets).
+// table (hashed source id, links << 20 | packets).  The counts take 2 bytes
+// per slot, two slots to a word: a bucket of fewer than 2^16 packets cannot
+// carry into its neighbour.  A larger bucket uses half the slots with a full
+// word each (same bytes).  The 6.5 KB per wavefront fit 24 wavefronts in a
+// compute unit's LDS, against 20 with 4-byte counts.
 __host__ __device__ constexpr size_t wave_lds_stride(uint32_t hist, uint32_t rows) {
-  return (size_t(WAVE_SLOTS) * 8 + size_t(WAVE_SLOTS) * 4 + 2 * size_t(hist) * 4 +
+  return (size_t(WAVE_SLOTS) * 8 + size_t(WAVE_SLOTS) * 2 + 2 * size_t(hist) * 4 +
           size_t(WAVE_SLOTS) * 2 + (rows ? size_t(WAVE_ROWS) * 8 : 0) + 15) &
          ~size_t(15);
 }
@@ -1417,18 +1421,29 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
   const uint32_t w = uniform(threadIdx.x >> 6), lane = lane_id();
   unsigned char* p = smem + size_t(w) * wave_lds_stride(hist, rows);
   u64* tk = reinterpret_cast<u64*>(p);             p += size_t(WAVE_SLOTS) * 8;
-  uint32_t* tc = reinterpret_cast<uint32_t*>(p);   p += size_t(WAVE_SLOTS) * 4;
+  uint32_t* tc = reinterpret_cast<uint32_t*>(p);   p += size_t(WAVE_SLOTS) * 2;   // see above
   uint32_t* histR = reinterpret_cast<uint32_t*>(p);  p += size_t(hist) * 4;
   uint32_t* histC = reinterpret_cast<uint32_t*>(p);  p += size_t(hist) * 4;
   uint16_t* occ = reinterpret_cast<uint16_t*>(p);    p += size_t(WAVE_SLOTS) * 2;
   uint32_t* rk = reinterpret_cast<uint32_t*>(p);     p += size_t(WAVE_ROWS) * 4;   // if rows
   uint32_t* rv = reinterpret_cast<uint32_t*>(p);
   constexpr uint32_t S = WAVE_SLOTS;
+  constexpr uint32_t TCW = WAVE_SLOTS / 2;   // count words
 
-  for (uint32_t i = lane; i < S; i += 64) {
-    tk[i] = EMPTY64;
-    tc[i] = 0;
-  }
+  // Count of slot s, and the empty count words.  A bucket of >= 2^16
+  // packets uses slots 0 .. S/2-1 with a word each: cw = 0 (else 1) and
+  // cmask = ~0 (else 0xFFFF), uniform, so no path branches on it.
+  uint32_t cw = 1, cmask = 0xFFFFu;
+  auto tcount = [&](uint32_t s) -> uint32_t {
+    return (tc[s >> cw] >> ((s & cw) << 4)) & cmask;
+  };
+  auto tcount_add = [&](uint32_t s) { lds_add(&tc[s >> cw], 1u << ((s & cw) << 4)); };
+  auto tclear = [&]() {
+    for (uint32_t i = lane; i < TCW; i += 64) tc[i] = 0;
+  };
+
+  for (uint32_t i = lane; i < S; i += 64) tk[i] = EMPTY64;
+  tclear();
   if (rows)
     for (uint32_t i = lane; i < WAVE_ROWS; i += 64) {
       rk[i] = EMPTY32;
@@ -1462,6 +1477,7 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
     uint32_t below = a0;
     for (uint32_t t = 64 + lane; t < nt; t += 64) below += tm0[t];
     below = uniform(wave_sum(below));
+    uint32_t smask = S - 1;   // the table's slots - 1 (set by each build)
 
     uint32_t n = 0;        // occupied slots (uniform)
     uint32_t special = 0;  // packets of the key equal to the empty marker (uniform)
@@ -1482,6 +1498,7 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
       special = 0;
       pk = 0;
       bool gave_up = false;
+      bool first = true;
       for (uint32_t g0 = 0; g0 < nt; g0 += 64) {
         const uint32_t t = g0 + lane;
         u64 mb = 0;
@@ -1495,6 +1512,14 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
         const uint32_t incl = wave_inclusive_scan(len);
         const uint32_t elems = uniform(readlane(incl, 63));
         pk += elems;
+        if (first) {   // 16-bit counts unless the bucket may reach 2^16 packets
+          first = false;
+          const bool wide = nt > 64 || elems >= 65536u;
+          cw = wide ? 0u : 1u;
+          cmask = wide ? ~0u : 0xFFFFu;
+          smask = wide ? S / 2 - 1 : S - 1;
+          probes = min(probes, smask + 1);
+        }
         const uint32_t start = incl - len;      // exclusive prefix: the segment's first element
         const u64 nonempty = __ballot(len > 0);
         mb -= start;                            // base minus exclusive prefix
@@ -1548,11 +1573,11 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
           }
           int slot[LINK_MAXU];
           bool fresh[LINK_MAXU];
-          if (!cas_insert<LINK_MAXU>(tk, S - 1, key, h, ok, slot, fresh, probes))
+          if (!cas_insert<LINK_MAXU>(tk, smask, key, h, ok, slot, fresh, probes))
             gave_up = true;
 #pragma unroll
           for (int u = 0; u < LINK_MAXU; ++u)
-            if (slot[u] >= 0) lds_add(&tc[slot[u]], 1);
+            if (slot[u] >= 0) tcount_add(uint32_t(slot[u]));
 #pragma unroll
           for (int u = 0; u < LINK_MAXU; ++u) {
             const u64 m = __ballot(fresh[u]);
@@ -1566,11 +1591,8 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
     };
 
     auto reset = [&]() {
-      for (uint32_t i = lane; i < n; i += 64) {
-        const uint32_t s = occ[i];
-        tk[s] = EMPTY64;
-        tc[s] = 0;
-      }
+      for (uint32_t i = lane; i < n; i += 64) tk[occ[i]] = EMPTY64;
+      tclear();
       n = 0;
       wave_fence();
     };
@@ -1580,7 +1602,7 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
     auto count = [&]() {
       for (uint32_t i = lane; i < n; i += 64) {
         const uint32_t s = occ[i];
-        const uint32_t c = tc[s];
+        const uint32_t c = tcount(s);
         sum += c;
         mx = max(mx, c);
         const u64 key = tk[s];
@@ -1636,7 +1658,7 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
               }
               at = (at + 1) & (WAVE_ROWS - 1);
             }
-            if (got >= 0) lds_add(&rv[got], (1u << 20) | tc[s]);
+            if (got >= 0) lds_add(&rv[got], (1u << 20) | tcount(s));
             else failed = true;
           }
         }
@@ -1667,9 +1689,8 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
       for (uint32_t i = lane; i < n; i += 64) {
         const uint32_t s = occ[i];
         const u64 key = tk[s];
-        const uint32_t cnt = tc[s];
+        const uint32_t cnt = tcount(s);
         tk[s] = EMPTY64;
-        tc[s] = 0;
         const uint32_t parts = entry_parts(cnt, 1);
         const uint32_t r = uint32_t(key >> 32);
         if (!local || r == EMPTY32) {
@@ -1708,6 +1729,7 @@ __global__ __launch_bounds__(WAVE_NT) void k_links_wave(nsgc_dev_plan* P, uint32
           }
         }
       }
+      tclear();   // after every read of the counts above (one wavefront, in order)
       n = 0;
       wave_fence();
     };

@@ -114,6 +114,33 @@ def test_heavy_contention_windows():
     check(src, dst, off, "contention", forms=("batched", "plain"))
 
 
+def test_wavefront_buckets_past_the_16_bit_counts():
+    # The wavefront phase B keeps two 16-bit counts per word; a bucket of
+    # 2^16 packets or more switches to half the slots with full-word counts.
+    # Windows whose hot bucket holds exactly 2^16 - 1 packets (the last
+    # narrow case), exactly 2^16, and far more, with and without other links.
+    rng = np.random.default_rng(41)
+    sizes = [65535, 65536, 1 << 17, 1 << 17, 1 << 18]
+    off = synth.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    src = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    dst = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    a = [int(x) for x in off]
+    src[a[0]:a[1]], dst[a[0]:a[1]] = 3, 4            # one link, 65535 packets
+    src[a[1]:a[2]], dst[a[1]:a[2]] = 3, 4            # one link, 65536 packets
+    src[a[2]:a[3]], dst[a[2]:a[3]] = 0xFFFFFFFF, 7   # one link of 2^17 packets
+    hot = a[3] + rng.choice(sizes[3], 70000, replace=False)
+    src[hot], dst[hot] = 11, 12                      # 70000 packets among 61072 others
+    hot = a[4] + rng.choice(sizes[4], 65535, replace=False)
+    src[hot], dst[hot] = 13, 14                      # 65535 packets among 196609 others
+    p = nsgc.plan_inspect(off)
+    assert (p["tier"] == 2).all()
+    # every window runs phase B one wavefront per 256-packet link bucket
+    assert [int(x) for x in p["log2_link_buckets"]] == [
+        int(np.ceil(np.log2(k / 256))) for k in sizes]
+    check(src, dst, off, "16-bit count limit", forms=("batched", "graph", "noalloc"))
+
+
 @pytest.mark.parametrize("maker", ["uniform_single", "zipf_batch", "skewed_large",
                                    "uneven_batch", "serving_stream"])
 def test_workloads_scaled_down(maker):
