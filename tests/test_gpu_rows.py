@@ -117,7 +117,8 @@ def test_more_sources_than_the_row_table_holds():
 def test_tuning_variants():
     wl = synth.zipf_batch(seed=4, num_windows=5, log2_window=15)
     src, dst = wl.generate()
-    sizes = [0, 1, 900, 1025, 3000, 20000, 1 << 15, 77777, 300000]
+    sizes = [0, 1, 300, 512, 900, 1025, 3000, 20000, 1 << 15, 77777, 300000]   # 300, 512:
+    # two link buckets when the small tier is off
     off = synth.offsets_from_sizes(sizes)
     s2, d2 = synth.fill(off, 9, wl.src_dist, wl.dst_dist)
     for name, extra in (("tiny buckets", dict(cls=[[2048, 4096, 4096, 64]] * 33,
