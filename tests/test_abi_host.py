@@ -195,6 +195,48 @@ def test_row_complete_plans_the_same_buckets_with_more_workspace():
         nsgc.set_tune(before)
 
 
+def test_host_calls_from_many_threads():
+    # host-only entry points called from several threads at once (ctypes
+    # releases the GIL): tuning switches interleave with planning, and every
+    # plan is one of the two tunings' plans
+    import threading
+    off = np.concatenate([[0], np.cumsum([3000, 1 << 17, 70000, 900, 1 << 20])]).astype(np.int64)
+    before = nsgc.get_tune()
+    a = nsgc.default_tune()
+    b = nsgc.Tune.from_dict(dict(a.to_dict(), max_link_buckets_log2=8, tile_log2=12))
+    try:
+        nsgc.set_tune(a)
+        want_a = nsgc.plan_inspect(off)
+        nsgc.set_tune(b)
+        want_b = nsgc.plan_inspect(off)
+        assert (want_a["log2_link_buckets"] != want_b["log2_link_buckets"]).any()
+        assert (want_a["tiles"] != want_b["tiles"]).any()
+        errors = []
+
+        def planner():
+            for _ in range(200):
+                got = nsgc.plan_inspect(off)
+                if not any(all((got[k] == w[k]).all() for k in ("tier", "log2_link_buckets", "tiles"))
+                           for w in (want_a, want_b)):
+                    errors.append(got)
+
+        def tuner():
+            for i in range(400):
+                nsgc.set_tune((a, b)[i % 2])
+                nsgc.get_tune()
+
+        threads = [threading.Thread(target=planner) for _ in range(4)] + [
+            threading.Thread(target=tuner) for _ in range(2)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(60)
+        assert not any(t.is_alive() for t in threads)
+        assert not errors
+    finally:
+        nsgc.set_tune(before)
+
+
 def test_plan_rejects_bad_offsets():
     with pytest.raises(nsgc.NsgcError):
         nsgc.plan_inspect(np.array([0, 5, 2], np.int64))
